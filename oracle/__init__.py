@@ -1,0 +1,330 @@
+"""CPU oracle for the slab-decomposed 3D real FFT.
+
+TEST INFRASTRUCTURE ONLY: the plain FP64 reference the GPU library is checked
+against.  Only ``tests/``, ``__graft_entry__.smoke()`` and the CPU-baseline leg
+of ``bench.py`` may import it.  It shares no code with the GPU library and
+never imports it.
+
+The arithmetic lives in ``oracle.c`` (FP64, one line at a time, OpenMP over
+lines); this module only composes the 1D transforms along the three axes and
+writes out the index permutations of the slab algorithm with numpy reshapes.
+
+Paper passages followed (Verma et al., "Scalable Multi-node Fast Fourier
+Transform on GPUs"):
+  * section 2, forward/inverse DFT equations: unnormalized sums with
+    exp(-/+ 2 pi i k.j / N);
+  * section 2, Hermitian symmetry of the transform of a real field: only
+    kz = 0..N/2 is stored (FFTW convention, K = N/2 + 1);
+  * section 2, slab decomposition: rank r owns x in [r N/p, (r+1) N/p);
+  * section 3, steps 1-5 of the forward algorithm: 2D R2C on every yz plane,
+    local xy transpose, all-to-all in chunks of (N/p) x (N/p) x K, chunk
+    transpose, strided 1D C2C along x; the inverse runs them in reverse order.
+
+Every function here is unnormalized; ``scale`` arguments multiply results.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "oracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+_lib = None
+
+DIRECT = 0
+RADIX2 = 1
+
+
+def build(force: bool = True) -> str:
+    """Compile oracle.c into liboracle.so with gcc and OpenMP."""
+    if force or not os.path.exists(_LIB):
+        tmp = _LIB + ".tmp"
+        subprocess.run(
+            ["gcc", "-O2", "-std=c11", "-D_GNU_SOURCE", "-fopenmp", "-fPIC",
+             "-shared", _SRC, "-o", tmp, "-lm"],
+            check=True)
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB):
+            build(force=True)
+        lib = ctypes.CDLL(_LIB)
+        i64, dp, ip = ctypes.c_int64, ctypes.c_void_p, ctypes.c_int
+        lib.oracle_c2c_axis.argtypes = [i64, i64, i64, dp, dp, ip, ip]
+        lib.oracle_r2c_rows.argtypes = [i64, i64, dp, dp, ip]
+        lib.oracle_c2r_rows.argtypes = [i64, i64, dp, dp, ip]
+        lib.oracle_zsum_rows.argtypes = [i64, i64, dp, i64, dp, dp]
+        for f in (lib.oracle_c2c_axis, lib.oracle_r2c_rows,
+                  lib.oracle_c2r_rows, lib.oracle_zsum_rows):
+            f.restype = ip
+        lib.oracle_num_threads.restype = ip
+        lib.oracle_set_num_threads.argtypes = [ip]
+        _lib = lib
+    return _lib
+
+
+def num_threads() -> int:
+    return int(_load().oracle_num_threads())
+
+
+def set_num_threads(n: int) -> None:
+    _load().oracle_set_num_threads(int(n))
+
+
+def _ptr(a: np.ndarray) -> int:
+    return a.ctypes.data
+
+
+def _pick(method, n):
+    if method is None:
+        return RADIX2 if n & (n - 1) == 0 else DIRECT
+    return method
+
+
+def c2c_axis(a: np.ndarray, axis: int, sign: int, method=None) -> np.ndarray:
+    """1D complex DFT along ``axis`` (sign -1 forward, +1 inverse), FP64."""
+    a = np.ascontiguousarray(a, dtype=np.complex128)
+    axis = axis % a.ndim
+    n = a.shape[axis]
+    b = int(np.prod(a.shape[:axis], dtype=np.int64))
+    m = int(np.prod(a.shape[axis + 1:], dtype=np.int64))
+    out = np.empty_like(a)
+    rc = _load().oracle_c2c_axis(b, n, m, _ptr(a), _ptr(out), int(sign),
+                                 _pick(method, n))
+    if rc:
+        raise ValueError("oracle_c2c_axis rejected its arguments")
+    return out
+
+
+def r2c_last(f: np.ndarray, method=None) -> np.ndarray:
+    """Real rows of length N along the last axis -> K = N//2 + 1 complex bins."""
+    f = np.ascontiguousarray(f, dtype=np.float64)
+    n = f.shape[-1]
+    rows = int(np.prod(f.shape[:-1], dtype=np.int64))
+    out = np.empty(f.shape[:-1] + (n // 2 + 1,), dtype=np.complex128)
+    if _load().oracle_r2c_rows(rows, n, _ptr(f), _ptr(out), _pick(method, n)):
+        raise ValueError("oracle_r2c_rows rejected its arguments")
+    return out
+
+
+def c2r_last(g: np.ndarray, n: int, method=None) -> np.ndarray:
+    """Half-spectrum rows (K = n//2 + 1 bins) -> n reals, w-weighted real part."""
+    g = np.ascontiguousarray(g, dtype=np.complex128)
+    if g.shape[-1] != n // 2 + 1:
+        raise ValueError("last axis must hold n//2 + 1 bins")
+    rows = int(np.prod(g.shape[:-1], dtype=np.int64))
+    out = np.empty(g.shape[:-1] + (n,), dtype=np.float64)
+    if _load().oracle_c2r_rows(rows, n, _ptr(g), _ptr(out), _pick(method, n)):
+        raise ValueError("oracle_c2r_rows rejected its arguments")
+    return out
+
+
+# --------------------------------------------------------------------------
+# 3D transforms of a full grid (section 2 equations, real field, half along z)
+# --------------------------------------------------------------------------
+
+def r2c3d(f: np.ndarray, method=None) -> np.ndarray:
+    """Forward DFT of a real [..., Nx, Ny, Nz] grid, kz = 0..Nz/2 kept.
+
+    Separable evaluation: real-to-half along z, then complex DFT along y,
+    then along x (leading axes, if any, are a batch).
+    """
+    g = r2c_last(f, method)
+    g = c2c_axis(g, -2, -1, method)
+    return c2c_axis(g, -3, -1, method)
+
+
+def c2r3d(g: np.ndarray, n: int, scale: float = 1.0, method=None) -> np.ndarray:
+    """Inverse DFT of a half spectrum [..., Nx, Ny, K] to a real grid.
+
+    Inverse complex DFT along x, then y, then the w-weighted real part along
+    z (the same order reversed, section 3).  Result times ``scale``.
+    """
+    h = c2c_axis(g, -3, +1, method)
+    h = c2c_axis(h, -2, +1, method)
+    f = c2r_last(h, n, method)
+    if scale != 1.0:
+        f *= scale
+    return f
+
+
+# --------------------------------------------------------------------------
+# One rank's share of the slab algorithm (section 3, steps 1-5)
+# --------------------------------------------------------------------------
+
+def r2c2d_planes(slab: np.ndarray, method=None) -> np.ndarray:
+    """Step 1: 2D R2C over (y, z) of every x-plane of a [..., X, N, N] slab."""
+    g = r2c_last(slab, method)
+    return c2c_axis(g, -2, -1, method)
+
+
+def c2r2d_planes(g: np.ndarray, n: int, scale: float = 1.0,
+                 method=None) -> np.ndarray:
+    """Inverse of step 1: inverse DFT along y, then C2R along z, times scale."""
+    h = c2c_axis(g, -2, +1, method)
+    f = c2r_last(h, n, method)
+    if scale != 1.0:
+        f *= scale
+    return f
+
+
+def pack_slab(s: np.ndarray, p: int, paper_order: bool = False) -> np.ndarray:
+    """Steps 2 and the chunking of step 3 as one permutation.
+
+    ``s`` is a rank's [..., X, N, K] half spectrum.  Chunk j holds the
+    wavenumbers ky in [j N/p, (j+1) N/p) of every local plane and is destined
+    for rank j.  Default order inside a chunk: [x_l][ky_l][kz]; with
+    ``paper_order`` the chunk holds [ky_l][x_l][kz], the order the paper's
+    local xy transpose produces.  Output shape [..., p, X, N/p, K] (or
+    [..., p, N/p, X, K]).
+    """
+    *lead, x, n, k = s.shape
+    if n % p:
+        raise ValueError("p must divide N")
+    y = n // p
+    t = s.reshape(*lead, x, p, y, k)
+    nl = len(lead)
+    # [.., x, j, y_l, k] -> [.., j, x, y_l, k]
+    perm = list(range(nl)) + [nl + 1, nl, nl + 2, nl + 3]
+    if paper_order:
+        perm = list(range(nl)) + [nl + 1, nl + 2, nl, nl + 3]
+    return np.ascontiguousarray(t.transpose(perm))
+
+
+def unpack_slab(send: np.ndarray, paper_order: bool = False) -> np.ndarray:
+    """Inverse permutation of :func:`pack_slab`."""
+    *lead, p, a, b, k = send.shape
+    nl = len(lead)
+    if paper_order:   # [j, y_l, x, k] -> [x, j, y_l, k]
+        perm = list(range(nl)) + [nl + 2, nl, nl + 1, nl + 3]
+        x, y = b, a
+    else:             # [j, x, y_l, k] -> [x, j, y_l, k]
+        perm = list(range(nl)) + [nl + 1, nl, nl + 2, nl + 3]
+        x, y = a, b
+    t = np.ascontiguousarray(send.transpose(perm))
+    return t.reshape(*lead, x, p * y, k)
+
+
+def exchange(sends: list[np.ndarray]) -> list[np.ndarray]:
+    """Step 3 on one host: rank r receives chunk r of every rank's send buffer.
+
+    ``sends[i]`` is rank i's [p, X, Y, K] buffer (default order).  The chunk
+    keeps its internal order; chunk order equals rank order.  Returns, per
+    rank r, the received [p, X, Y, K] buffer, which read as [N, Y, K] (x
+    slowest) is the x-pencil of step 5 with no chunk transpose needed.
+    """
+    p = len(sends)
+    return [np.stack([sends[i][r] for i in range(p)]) for r in range(p)]
+
+
+def x_c2c(pencil: np.ndarray, sign: int, method=None) -> np.ndarray:
+    """Step 5: strided batched 1D DFT along x of an [..., N, Y, K] pencil."""
+    return c2c_axis(pencil, -3, sign, method)
+
+
+# --------------------------------------------------------------------------
+# Weights, adjoints and the differentiable workloads
+# --------------------------------------------------------------------------
+
+def half_weights(n: int) -> np.ndarray:
+    """w(kz) of the stored half spectrum: 1 at kz = 0 and kz = N/2, else 2."""
+    k = np.arange(n // 2 + 1)
+    w = np.full(k.shape, 2.0)
+    w[0] = 1.0
+    if n % 2 == 0:
+        w[-1] = 1.0
+    return w
+
+
+def r2c3d_adjoint(g: np.ndarray, n: int, method=None) -> np.ndarray:
+    """Adjoint of the forward R2C for <F,G> = sum over the half of Re(F* G).
+
+    R2C^T(G)(j) = sum_{k in half} Re(G(k) exp(+2 pi i k.j/N)) = C2R(G / w).
+    """
+    return c2r3d(np.asarray(g) / half_weights(n), n, 1.0, method)
+
+
+def c2r3d_adjoint(h: np.ndarray, method=None) -> np.ndarray:
+    """Adjoint of C2R: C2R^T(h) = w * R2C(h)."""
+    n = h.shape[-1]
+    return r2c3d(h, method) * half_weights(n)
+
+
+def wavenumbers(n: int):
+    """Signed integer wavenumbers along x/y (length n) and z (n//2 + 1)."""
+    k = np.arange(n)
+    kxy = np.where(k <= n // 2, k, k - n).astype(np.float64)
+    kz = np.arange(n // 2 + 1, dtype=np.float64)
+    return kxy, kz
+
+
+def k_squared(n: int) -> np.ndarray:
+    kxy, kz = wavenumbers(n)
+    return (kxy[:, None, None] ** 2 + kxy[None, :, None] ** 2
+            + kz[None, None, :] ** 2)
+
+
+def energy_loss(u: np.ndarray) -> float:
+    """L1(u) = sum over the full spectrum of |k|^2 |u_hat(k)|^2.
+
+    Over the stored half this is sum w(kz) |k|^2 |u_hat|^2 (the bins kz and
+    -kz carry equal energy for a real field).
+    """
+    n = u.shape[-1]
+    uh = r2c3d(u)
+    return float(np.sum(half_weights(n) * k_squared(n) * np.abs(uh) ** 2))
+
+
+def energy_loss_grad(u: np.ndarray) -> np.ndarray:
+    """dL1/du = 2 C2R(|k|^2 u_hat) (unnormalized C2R)."""
+    n = u.shape[-1]
+    return 2.0 * c2r3d(k_squared(n) * r2c3d(u), n)
+
+
+def poisson(f: np.ndarray) -> np.ndarray:
+    """Spectral Poisson solve: u = N^-3 C2R(m R2C(f)), m = -1/|k|^2, m(0) = 0."""
+    n = f.shape[-1]
+    k2 = k_squared(n)
+    m = np.zeros_like(k2)
+    nz = k2 > 0
+    m[nz] = -1.0 / k2[nz]
+    return c2r3d(m * r2c3d(f), n, 1.0 / n ** 3)
+
+
+def poisson_loss(f: np.ndarray) -> float:
+    """L2(f) = sum_j u(j)^2 with u = poisson(f)."""
+    return float(np.sum(poisson(f) ** 2))
+
+
+def poisson_loss_grad(f: np.ndarray) -> np.ndarray:
+    """dL2/df = 2 poisson(poisson(f)): the solve is self-adjoint."""
+    return 2.0 * poisson(poisson(f))
+
+
+# --------------------------------------------------------------------------
+# Sampled checks of large transforms
+# --------------------------------------------------------------------------
+
+def r2c3d_kz_planes(f: np.ndarray, kz) -> np.ndarray:
+    """Whole kz-planes F(:, :, kz_q) of the forward R2C of a real [N,N,N] grid.
+
+    The z sum of the forward equation is evaluated directly for the requested
+    kz only, then the complex DFT along y and along x.  Returns [N, N, nq].
+    """
+    f = np.ascontiguousarray(f, dtype=np.float64)
+    nx, ny, n = f.shape
+    kz = np.ascontiguousarray(np.asarray(kz, dtype=np.int64))
+    a = np.empty((nx, ny, kz.size), dtype=np.complex128)
+    if _load().oracle_zsum_rows(nx * ny, n, _ptr(f), kz.size, _ptr(kz),
+                                _ptr(a)):
+        raise ValueError("oracle_zsum_rows rejected its arguments")
+    a = c2c_axis(a, 1, -1)
+    return c2c_axis(a, 0, -1)

@@ -1,0 +1,223 @@
+"""Benchmark: 3D R2C + C2R round trip of a 1024^3 FP64 grid on one MI355X.
+
+One step = the whole hot path once: forward R2C (z pass, y pass, x pass)
+and inverse C2R (x, y, z passes with the 1/N^3 normalization fused), on a
+synthetic seeded uniform[-1,1) field already resident in HBM.  Each pass is
+bracketed by HIP events on the stream it is launched on, inside the timed
+region, so the per-kernel durations below are live measurements.
+
+Prints ONE JSON line (rank 0).  Run ``python bench.py --help`` for options.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import torch
+
+PEAK_HBM_GBS = 8000.0   # MI355X HBM3E, published
+
+METRIC = ("3D R2C+C2R GFLOP/s and % HBM roofline per GPU at 1024^3 FP64 "
+          "(vs FP32/adjoint)")
+
+
+def parse():
+    ap = argparse.ArgumentParser(description=__doc__)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--n", type=int, default=1024)
+    ap.add_argument("--dtype", choices=["f64", "f32"], default="f64")
+    ap.add_argument("--seed", type=int, default=3)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-planes", type=int, default=256,
+                    help="x-planes (and pencil columns) in the oracle sample")
+    ap.add_argument("--traffic", default=None,
+                    help="JSON file with per-kernel HBM bytes from rocprofv3")
+    return ap.parse_args()
+
+
+def gflop_pair(n: int) -> float:
+    """5 (N^3/2) log2 N^3 per R2C, twice per forward+inverse pair."""
+    return 2 * 5.0 * (n ** 3 / 2) * math.log2(n ** 3) / 1e9
+
+
+def cpu_baseline(n: int, planes: int, seed: int) -> dict:
+    """Time the FP64 oracle on a bounded sample of the same workload.
+
+    Sample: the forward 2D R2C (z and y lines) and its inverse on `planes`
+    x-planes of the N^3 grid, plus the forward and inverse x lines of a
+    [N][planes][K] pencil.  The nominal flop count of those lines (one third
+    of 5 (N^3/2) log2 N^3 per axis, pro rata) over the wall time gives a
+    rate in the metric's unit.
+    """
+    import numpy as np
+
+    import oracle
+    import synth
+
+    k = n // 2 + 1
+    f = synth.uniform((planes, n, n), seed, torch.float64).numpy()
+    pen = (synth.uniform((n, planes, k), seed + 1, torch.float64).numpy()
+           + 1j * synth.uniform((n, planes, k), seed + 2, torch.float64).numpy())
+    t0 = time.perf_counter()
+    g = oracle.r2c2d_planes(f)
+    oracle.c2r2d_planes(g, n, 1.0 / n ** 3)
+    h = oracle.x_c2c(pen, -1)
+    oracle.x_c2c(h, +1)
+    dt = time.perf_counter() - t0
+    per_axis_pair = gflop_pair(n) / 3.0
+    work = per_axis_pair * (2 * planes / n + planes / n)
+    return {"value": round(work / dt, 3), "unit": "GFLOP/s",
+            "cores": oracle.num_threads(), "kind": "oracle",
+            "sample": (f"radix-2 FP64 oracle: 2D R2C+C2R on {planes} of {n} "
+                       f"x-planes and x-line C2C fwd+inv on a [{n}][{planes}][{k}] "
+                       f"pencil; {dt:.2f} s wall, rate = nominal flops of those "
+                       f"lines / time"),
+            "seconds": round(dt, 3)}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU's share of the transform; --gpus "
+              f"{args.gpus} is not supported (this build drives one GPU, and the "
+              f"multi-GPU exchange is not part of it).", file=sys.stderr)
+        sys.exit(2)
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(2)
+
+    import synth
+    from paper_2202_12756_amd import Plan
+
+    n = args.n
+    dtype = torch.float64 if args.dtype == "f64" else torch.float32
+    b = 8 if dtype == torch.float64 else 4
+    k = n // 2 + 1
+    dev = torch.device("cuda", 0)
+    torch.cuda.set_device(dev)
+    plan = Plan(n, dtype, device=dev)
+    x = synth.uniform(plan.real_shape, args.seed, dtype, dev)
+    F = plan.empty_spectrum()
+    y = plan.empty_real()
+    scale = 1.0 / n ** 3
+    stream = torch.cuda.current_stream(dev)
+    print(f"[bench] n={n} dtype={args.dtype} input ready; warmup {args.warmup}",
+          file=sys.stderr, flush=True)
+
+    passes = ["z_r2c", "y_fwd", "x_fwd", "x_inv", "y_inv", "z_c2r"]
+
+    def step(ev=None):
+        if ev is not None:
+            ev[0].record(stream)
+        plan.z_r2c(x, F)
+        if ev is not None:
+            ev[1].record(stream)
+        plan.y_c2c(F, -1)
+        if ev is not None:
+            ev[2].record(stream)
+        plan.x_c2c(F, -1)
+        if ev is not None:
+            ev[3].record(stream)
+        plan.x_c2c(F, +1)
+        if ev is not None:
+            ev[4].record(stream)
+        plan.y_c2c(F, +1)
+        if ev is not None:
+            ev[5].record(stream)
+        plan.z_c2r(F, y, scale)
+        if ev is not None:
+            ev[6].record(stream)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+
+    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(7)]
+           for _ in range(args.steps)]
+    if torch.distributed.is_available() and torch.distributed.is_initialized():
+        torch.distributed.barrier()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for s in range(args.steps):
+        step(evs[s])
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    if torch.distributed.is_available() and torch.distributed.is_initialized():
+        torch.distributed.barrier()
+
+    per_pass = {p: 0.0 for p in passes}
+    for ev in evs:
+        for i, p in enumerate(passes):
+            per_pass[p] += ev[i].elapsed_time(ev[i + 1])
+    per_pass = {p: v / args.steps for p, v in per_pass.items()}
+    ms_step = wall * 1e3 / args.steps
+    ms_events = sum(per_pass.values())
+
+    # correctness of the measured work (outside the timed region)
+    err = (y - x).abs().max().item()
+    rel = (torch.linalg.vector_norm(y - x) / torch.linalg.vector_norm(x)).item()
+
+    R = n ** 3 * b
+    C = n * n * k * 2 * b
+    bytes_pass = {"z_r2c": R + C, "y_fwd": 2 * C, "x_fwd": 2 * C,
+                  "x_inv": 2 * C, "y_inv": 2 * C, "z_c2r": C + R}
+    kernel_name = {"z_r2c": "k_z_r2c", "y_fwd": "k_strided", "x_fwd": "k_strided",
+                   "x_inv": "k_strided", "y_inv": "k_strided", "z_c2r": "k_z_c2r"}
+    gbs = {p: bytes_pass[p] / (per_pass[p] * 1e-3) / 1e9 for p in passes}
+    dom = max(passes, key=lambda p: per_pass[p])
+    traffic = None
+    if args.traffic and os.path.exists(args.traffic):
+        with open(args.traffic) as fh:
+            traffic = json.load(fh).get(dom)
+
+    gflop = gflop_pair(n)
+    model_bytes = 2 * (R + 5 * C)
+    line = {
+        "metric": METRIC,
+        "value": round(gflop / (ms_step * 1e-3), 2),
+        "unit": "GFLOP/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_step, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": args.dtype,
+        "data": "synthetic",
+        "config": {"workload": (f"{n}^3 real {args.dtype.upper()} grid held whole on one "
+                                f"GPU, seeded uniform[-1,1) (SplitMix64 seed "
+                                f"{args.seed}); forward R2C + inverse C2R with 1/N^3"),
+                   "n": n, "slab_x": n, "batch": 1},
+        "roofline": {"bound": "hbm",
+                     "kernel": f"{kernel_name[dom]} ({dom})",
+                     "achieved": round(gbs[dom], 1),
+                     "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                     "frac": round(gbs[dom] / PEAK_HBM_GBS, 4),
+                     "traffic": traffic,
+                     "algorithmic_bytes_per_launch": bytes_pass[dom],
+                     "avg_launch_ms": round(per_pass[dom], 4)},
+        "per_pass_ms": {p: round(v, 4) for p, v in per_pass.items()},
+        "per_pass_GBps": {p: round(v, 1) for p, v in gbs.items()},
+        "pair_hbm_roofline_frac": round(model_bytes / (ms_step * 1e-3) / 1e9
+                                        / PEAK_HBM_GBS, 4),
+        "model_bytes_per_pair": model_bytes,
+        "event_ms_per_step": round(ms_events, 4),
+        "paper_convention_GFLOPs": round(2 * gflop / (ms_step * 1e-3), 2),
+        "roundtrip_maxabs": err,
+        "roundtrip_rel_l2": rel,
+    }
+    if not args.no_cpu_baseline:
+        print("[bench] timing the CPU oracle sample", file=sys.stderr, flush=True)
+        line["cpu_baseline"] = cpu_baseline(n, args.cpu_planes, args.seed)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,212 @@
+/*
+ * gfft: one GPU's share of a slab-decomposed 3D real FFT on AMD Instinct
+ * MI355X (gfx950).
+ *
+ * The method is the slab algorithm of Verma et al., "Scalable Multi-node
+ * Fast Fourier Transform on GPUs" (section 3): a real N^3 field is split
+ * into x-slabs of X = N/p planes; each GPU runs a 2D real-to-complex FFT
+ * over (y, z) on its planes (step 1), reorders the result into p contiguous
+ * chunks of (N/p) x (N/p) x (N/2+1) complex values for the all-to-all
+ * exchange (steps 2-4), and finishes with a strided batched 1D complex FFT
+ * along x (step 5).  The inverse runs the same steps in reverse order.  The
+ * transforms are the unnormalized DFTs of section 2; because the field is
+ * real only kz = 0..N/2 is stored (FFTW convention, K = N/2 + 1).
+ *
+ * Conventions used by every entry point
+ *   - Arrays are C order, z fastest, x slowest.  A real grid is [X][N][N];
+ *     its half spectrum is [X][N][K]; complex values are interleaved
+ *     (re, im) pairs of the plan's real type.  A plan with batch B > 1
+ *     processes B independent grids stored back to back.
+ *   - All array pointers are DEVICE pointers owned by the caller, aligned to
+ *     at least 16 bytes.  The library never allocates, frees, copies to the
+ *     host or synchronizes inside an exec call; it only enqueues kernels on
+ *     `stream` (a hipStream_t; NULL means the null stream).
+ *   - Every argument is checked on the host before any HIP call, and every
+ *     call returns a gfft_status; nothing is thrown and nothing aborts.  A
+ *     failed kernel launch returns GFFT_E_HIP.  Errors raised while a kernel
+ *     runs are reported by the caller's next synchronization.
+ *   - Plans are immutable after creation: concurrent exec calls on one plan
+ *     are safe when they use different streams and disjoint buffers.
+ */
+#ifndef GFFT_H
+#define GFFT_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    GFFT_OK = 0,
+    GFFT_E_INVALID_ARG = -1, /* NULL pointer, bad sign, aliasing, bad enum  */
+    GFFT_E_UNSUPPORTED = -2, /* size/flag combination this build lacks      */
+    GFFT_E_ALIGN = -3,       /* a data pointer is not 16-byte aligned       */
+    GFFT_E_NOMEM = -4,       /* plan tables could not be allocated          */
+    GFFT_E_HIP = -5,         /* a HIP runtime call or kernel launch failed  */
+    GFFT_E_NO_DEVICE = -6    /* no usable gfx950 device is present          */
+} gfft_status;
+
+typedef enum { GFFT_F64 = 0, GFFT_F32 = 1 } gfft_dtype;
+
+/* Plan flags. */
+enum {
+    /* Slab plans: exec_r2c leaves the half spectrum in all-to-all send order
+     * [p][X][N/p][K] (chunk j = wavenumbers ky in [j N/p, (j+1) N/p), one
+     * chunk per destination rank, section 3 steps 2-3), and exec_c2r reads
+     * that order.  The reorder is folded into the z pass's stores/loads, so
+     * it costs no extra pass. */
+    GFFT_FUSE_PACK = 1u << 0
+};
+
+typedef struct gfft_plan gfft_plan;
+
+/* Byte sizes of the caller-owned buffers a plan works on. */
+typedef struct {
+    int64_t n;             /* grid edge N                                  */
+    int64_t slab_x;        /* X = local x-planes                           */
+    int64_t ranks;         /* p = N / X                                    */
+    int64_t batch;         /* independent grids                            */
+    int64_t k;             /* K = N/2 + 1                                  */
+    int64_t real_bytes;    /* batch * X * N * N reals                      */
+    int64_t complex_bytes; /* batch * X * N * K complex (= send buffer)    */
+    int64_t pencil_bytes;  /* batch * N * (N/p) * K complex, x-pencil      */
+    int64_t chunk_bytes;   /* one all-to-all chunk: X * (N/p) * K complex  */
+} gfft_plan_sizes;
+
+/*
+ * Create a plan for one GPU's share of an N^3 real grid.
+ *   n      : grid edge, a power of two with 16 <= n <= 4096 (the paper runs
+ *            1024^3-4096^3; all sizes it uses are powers of two, section 2).
+ *   dtype  : GFFT_F64 or GFFT_F32, the type of the data and the arithmetic.
+ *   slab_x : local x-planes X; must divide n.  X == n is the full grid on
+ *            one GPU (p = 1); X < n is rank r's slab of p = n/X ranks
+ *            (section 2, slab decomposition).
+ *   batch  : >= 1 independent grids per exec call.
+ *   flags  : bitwise OR of GFFT_FUSE_PACK (or 0).
+ * On success *out receives the plan.  The plan owns small device tables
+ * (FP64-derived twiddle factors rounded once to the working precision) on
+ * the device that is current at creation; exec calls must run with that
+ * device current.
+ */
+gfft_status gfft_plan_create(gfft_plan **out, int64_t n, gfft_dtype dtype,
+                             int64_t slab_x, int64_t batch, uint32_t flags);
+
+/* Free a plan and its tables (NULL is accepted).  The caller must ensure no
+ * work using the plan is still queued. */
+gfft_status gfft_plan_destroy(gfft_plan *plan);
+
+/* Fill *sizes with the plan's dimensions and buffer sizes. */
+gfft_status gfft_plan_query(const gfft_plan *plan, gfft_plan_sizes *sizes);
+
+/*
+ * Forward transform, section 2 forward equation, unnormalized.
+ *   in_real  : [batch][X][N][N] reals, not modified.
+ *   out_cplx : [batch][X][N][K] complex (send order with GFFT_FUSE_PACK).
+ * Full grid (X == N): the whole 3D R2C, output F(kx, ky, kz) in natural
+ * order.  Slab (X < N): section 3 step 1, the 2D R2C over (y, z) of each
+ * local plane; steps 2-4 are the caller's exchange; step 5 is
+ * gfft_exec_x_c2c on the received pencil.
+ * in_real and out_cplx must not overlap.
+ */
+gfft_status gfft_exec_r2c(const gfft_plan *plan, const void *in_real,
+                          void *out_cplx, void *stream);
+
+/*
+ * Inverse transform, section 2 inverse equation, unnormalized, times scale
+ * (scale = 1/N^3 gives back the field after a forward pass; the paper's
+ * separate normalization step, section 4).  For a half spectrum G that is
+ * not Hermitian the result is
+ *   f(j) = scale * sum_{k in half} w(kz) Re(G(k) exp(+2 pi i k.j / N)),
+ *   w(0) = w(N/2) = 1, w = 2 otherwise,
+ * i.e. the inverse DFT of G's Hermitian extension.
+ *   in_cplx  : [batch][X][N][K] complex (send order with GFFT_FUSE_PACK).
+ *              CLOBBERED: the y (and x) passes run in place on it.
+ *   out_real : [batch][X][N][N] reals.  Must not overlap in_cplx.
+ * Slab plans run the inverse of step 1 only (see gfft_exec_r2c).
+ */
+gfft_status gfft_exec_c2r(const gfft_plan *plan, void *in_cplx,
+                          void *out_real, double scale, void *stream);
+
+/*
+ * Adjoint of the forward transform under the real inner products
+ * <F,G> = sum_{k in half} Re(conj(F) G) and <f,h> = sum_j f h:
+ *   out_real = scale * R2C^T(G) = scale * C2R(G / w).
+ * Same layouts, aliasing rules and clobbering as gfft_exec_c2r.  This is
+ * the gradient of a real loss through the forward transform when G holds
+ * dL/dRe F + i dL/dIm F.
+ */
+gfft_status gfft_exec_r2c_adjoint(const gfft_plan *plan, void *in_cplx,
+                                  void *out_real, double scale, void *stream);
+
+/*
+ * Adjoint of the inverse transform: out_cplx = scale * w * R2C(h), the
+ * gradient of a real loss through gfft_exec_c2r(..., scale, ...) when h
+ * holds dL/df.  Same layouts and aliasing rules as gfft_exec_r2c.
+ */
+gfft_status gfft_exec_c2r_adjoint(const gfft_plan *plan, const void *in_real,
+                                  void *out_cplx, double scale, void *stream);
+
+/*
+ * Section 3 steps 2-3 as one permutation (standalone form of what
+ * GFFT_FUSE_PACK folds into the z pass): from a slab's natural half
+ * spectrum S[X][N][K], write p contiguous chunks
+ *   send[j][x_l][y_l][kz] = S[x_l][j*(N/p) + y_l][kz],   j = 0..p-1,
+ * chunk j destined for rank j.  Inside a chunk the order is [x_l][y_l][kz]:
+ * after the exchange, rank r's received chunks read as one [N][N/p][K]
+ * pencil (x slowest), so the paper's chunk transpose (step 4) is not needed.
+ * A pure copy: bit-exact.  Per batch entry; buffers of plan complex_bytes;
+ * they must not overlap.
+ */
+gfft_status gfft_pack_slab_for_alltoall(const gfft_plan *plan,
+                                        const void *slab_cplx,
+                                        void *send_blocks, void *stream);
+
+/* Inverse permutation of gfft_pack_slab_for_alltoall (for the inverse
+ * transform's return trip).  Bit-exact; buffers must not overlap. */
+gfft_status gfft_unpack_slab_from_alltoall(const gfft_plan *plan,
+                                           const void *recv_blocks,
+                                           void *slab_cplx, void *stream);
+
+/*
+ * Section 3 step 5: in-place strided batched 1D complex FFT along x of the
+ * pencil [batch][N][N/p][K] (x slowest, stride (N/p)*K), sign -1 forward,
+ * +1 inverse, unnormalized.  For a full-grid plan (p = 1) this is the x
+ * pass of the 3D transform on [N][N][K].
+ */
+gfft_status gfft_exec_x_c2c(const gfft_plan *plan, void *pencil, int sign,
+                            void *stream);
+
+/*
+ * The individual passes, for timing each one and for composing the slab
+ * pipeline by hand.  `data`/`in`/`out` follow the layouts above; the y pass
+ * works in place on [batch][X][N][K] (send order with GFFT_FUSE_PACK).
+ *   gfft_exec_z_r2c : rows of N reals -> rows of K complex (send-order
+ *                     rows with GFFT_FUSE_PACK), times scale on every bin
+ *                     and an extra factor 2 on 0 < kz < N/2 when weighted
+ *                     is nonzero (the w of the adjoint).
+ *   gfft_exec_y_c2c : 1D FFT along y, sign -1 or +1.
+ *   gfft_exec_z_c2r : rows of K complex -> N reals with Im of kz = 0 and
+ *                     kz = N/2 discarded, times scale, bins 0 < kz < N/2
+ *                     halved first when weighted is nonzero.
+ */
+gfft_status gfft_exec_z_r2c(const gfft_plan *plan, const void *in_real,
+                            void *out_cplx, double scale, int weighted,
+                            void *stream);
+gfft_status gfft_exec_y_c2c(const gfft_plan *plan, void *data, int sign,
+                            void *stream);
+gfft_status gfft_exec_z_c2r(const gfft_plan *plan, const void *in_cplx,
+                            void *out_real, double scale, int weighted,
+                            void *stream);
+
+/* Static description of a status code (never NULL). */
+const char *gfft_status_string(gfft_status status);
+
+/* Library version as major*10000 + minor*100 + patch. */
+int gfft_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* GFFT_H */

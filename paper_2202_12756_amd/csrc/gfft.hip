@@ -1,0 +1,354 @@
+// C ABI of the slab 3D real FFT: plans, argument checks and pass sequencing.
+// Every argument is validated on the host before the first HIP call.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdint>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "../../include/gfft.h"
+#include "kernels.h"
+
+struct gfft_plan {
+    int64_t n, x, p, y, batch, k;
+    int lg_n, lg_x, lg_y, lg_p;
+    gfft_dtype dtype;
+    uint32_t flags;
+    int device;
+    void* tw;  // W_N^m, m = 0..N-1, in the working precision
+};
+
+namespace {
+
+constexpr uint32_t kKnownFlags = GFFT_FUSE_PACK;
+
+int ilog2(int64_t v) {
+    int l = 0;
+    while ((int64_t(1) << l) < v) ++l;
+    return l;
+}
+bool pow2(int64_t v) { return v > 0 && (v & (v - 1)) == 0; }
+
+// exp(-2 pi i m / n) for a power of two n >= 4: reduce to a quadrant and to
+// an angle of at most pi/4 in exact integer arithmetic, evaluate in long
+// double, round once to double.
+void unit_root(int64_t m, int64_t n, double* re, double* im) {
+    const int64_t q4 = n / 4;
+    const int64_t quad = (m / q4) & 3;
+    const int64_t r = m % q4;  // angle 2 pi r / n in [0, pi/2)
+    long double c, s;
+    const long double two_pi = 6.283185307179586476925286766559005768L;
+    if (2 * r <= q4) {
+        const long double a = two_pi * (long double)r / (long double)n;
+        c = cosl(a);
+        s = sinl(a);
+    } else {  // pi/2 - a' with a' <= pi/4
+        const long double a = two_pi * (long double)(q4 - r) / (long double)n;
+        c = sinl(a);
+        s = cosl(a);
+    }
+    long double cr, ci;  // (c + i s) * i^quad = exp(+i theta)
+    switch (quad) {
+        case 0: cr = c; ci = s; break;
+        case 1: cr = -s; ci = c; break;
+        case 2: cr = -c; ci = -s; break;
+        default: cr = s; ci = -c; break;
+    }
+    *re = (double)cr;
+    *im = -(double)ci;
+}
+
+bool aligned16(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 15u) == 0; }
+
+gfft_status check_ptr(const void* p) {
+    if (!p) return GFFT_E_INVALID_ARG;
+    if (!aligned16(p)) return GFFT_E_ALIGN;
+    return GFFT_OK;
+}
+
+bool overlap(const void* a, int64_t na, const void* b, int64_t nb) {
+    const uintptr_t x = reinterpret_cast<uintptr_t>(a), y = reinterpret_cast<uintptr_t>(b);
+    return x < y + uint64_t(nb) && y < x + uint64_t(na);
+}
+
+int64_t real_size(const gfft_plan* p) { return p->batch * p->x * p->n * p->n; }
+int64_t cplx_count(const gfft_plan* p) { return p->batch * p->x * p->n * p->k; }
+int64_t elt(const gfft_plan* p) { return p->dtype == GFFT_F64 ? 8 : 4; }
+int64_t real_bytes(const gfft_plan* p) { return real_size(p) * elt(p); }
+int64_t cplx_bytes(const gfft_plan* p) { return cplx_count(p) * 2 * elt(p); }
+
+gfft::row_map zmap(const gfft_plan* p) {
+    const bool packed = (p->flags & GFFT_FUSE_PACK) != 0;
+    return gfft::row_map{p->lg_n, p->lg_x, packed ? p->lg_y : p->lg_n};
+}
+
+// y lines of a [batch][X][N][K] half spectrum, natural or send order.
+gfft::line_map ymap(const gfft_plan* p) {
+    const bool packed = (p->flags & GFFT_FUSE_PACK) != 0;
+    const int64_t yy = packed ? p->y : p->n;
+    gfft::line_map lm;
+    lm.b_hi = p->x * p->n * p->k;
+    lm.b_lo = yy * p->k;
+    lm.s_hi = p->x * yy * p->k;
+    lm.s_lo = p->k;
+    lm.lg_bx = p->lg_x;
+    lm.lg_y = packed ? p->lg_y : p->lg_n;
+    return lm;
+}
+
+// x lines of a [batch][N][Y][K] pencil.
+gfft::line_map xmap(const gfft_plan* p) {
+    gfft::line_map lm;
+    lm.b_hi = p->n * p->y * p->k;
+    lm.b_lo = 0;
+    lm.s_hi = 0;
+    lm.s_lo = p->y * p->k;
+    lm.lg_bx = 0;
+    lm.lg_y = p->lg_n;
+    return lm;
+}
+
+gfft_status hip_status(hipError_t e) { return e == hipSuccess ? GFFT_OK : GFFT_E_HIP; }
+
+hipStream_t as_stream(void* s) { return static_cast<hipStream_t>(s); }
+
+bool f64(const gfft_plan* p) { return p->dtype == GFFT_F64; }
+
+gfft_status run_z_r2c(const gfft_plan* p, const void* in, void* out, double scale,
+                      bool weighted, hipStream_t s) {
+    const double me = scale, mi = weighted ? 2.0 * scale : scale;
+    return hip_status(gfft::launch_z_r2c(f64(p), int(p->n), in, out, p->tw,
+                                         p->batch * p->x * p->n, zmap(p), me, mi, s));
+}
+
+gfft_status run_z_c2r(const gfft_plan* p, const void* in, void* out, double scale,
+                      bool weighted, hipStream_t s) {
+    const double me = scale, mi = weighted ? 0.5 * scale : scale;
+    return hip_status(gfft::launch_z_c2r(f64(p), int(p->n), in, out, p->tw,
+                                         p->batch * p->x * p->n, zmap(p), me, mi, s));
+}
+
+gfft_status run_y(const gfft_plan* p, void* data, int sign, hipStream_t s) {
+    return hip_status(gfft::launch_strided(f64(p), int(p->n), sign, data, p->tw, p->k,
+                                           p->batch * p->x, ymap(p), s));
+}
+
+gfft_status run_x(const gfft_plan* p, void* data, int sign, hipStream_t s) {
+    return hip_status(gfft::launch_strided(f64(p), int(p->n), sign, data, p->tw,
+                                           p->y * p->k, p->batch, xmap(p), s));
+}
+
+gfft_status check_r2c_args(const gfft_plan* p, const void* in, const void* out) {
+    if (!p) return GFFT_E_INVALID_ARG;
+    gfft_status st = check_ptr(in);
+    if (st != GFFT_OK) return st;
+    if ((st = check_ptr(out)) != GFFT_OK) return st;
+    if (overlap(in, real_bytes(p), out, cplx_bytes(p))) return GFFT_E_INVALID_ARG;
+    return GFFT_OK;
+}
+
+gfft_status forward(const gfft_plan* p, const void* in, void* out, double scale,
+                    bool weighted, void* stream) {
+    gfft_status st = check_r2c_args(p, in, out);
+    if (st != GFFT_OK) return st;
+    if (!std::isfinite(scale)) return GFFT_E_INVALID_ARG;
+    hipStream_t s = as_stream(stream);
+    if ((st = run_z_r2c(p, in, out, scale, weighted, s)) != GFFT_OK) return st;
+    if ((st = run_y(p, out, -1, s)) != GFFT_OK) return st;
+    if (p->p == 1) st = run_x(p, out, -1, s);
+    return st;
+}
+
+gfft_status inverse(const gfft_plan* p, void* in, void* out, double scale, bool weighted,
+                    void* stream) {
+    gfft_status st = check_r2c_args(p, out, in);
+    if (st != GFFT_OK) return st;
+    if (!std::isfinite(scale)) return GFFT_E_INVALID_ARG;
+    hipStream_t s = as_stream(stream);
+    if (p->p == 1 && (st = run_x(p, in, +1, s)) != GFFT_OK) return st;
+    if ((st = run_y(p, in, +1, s)) != GFFT_OK) return st;
+    return run_z_c2r(p, in, out, scale, weighted, s);
+}
+
+}  // namespace
+
+extern "C" {
+
+int gfft_version(void) { return 100; }
+
+const char* gfft_status_string(gfft_status st) {
+    switch (st) {
+        case GFFT_OK: return "success";
+        case GFFT_E_INVALID_ARG: return "invalid argument";
+        case GFFT_E_UNSUPPORTED: return "unsupported size or flag combination";
+        case GFFT_E_ALIGN: return "data pointer not 16-byte aligned";
+        case GFFT_E_NOMEM: return "out of device memory for plan tables";
+        case GFFT_E_HIP: return "HIP runtime or kernel launch failure";
+        case GFFT_E_NO_DEVICE: return "no usable gfx950 device";
+    }
+    return "unknown status";
+}
+
+gfft_status gfft_plan_create(gfft_plan** out, int64_t n, gfft_dtype dtype, int64_t slab_x,
+                             int64_t batch, uint32_t flags) {
+    if (!out) return GFFT_E_INVALID_ARG;
+    *out = nullptr;
+    if (dtype != GFFT_F64 && dtype != GFFT_F32) return GFFT_E_INVALID_ARG;
+    if (flags & ~kKnownFlags) return GFFT_E_INVALID_ARG;
+    if (batch < 1 || slab_x < 1 || n < 1) return GFFT_E_INVALID_ARG;
+    if (!pow2(n) || n < 16 || n > 4096) return GFFT_E_UNSUPPORTED;
+    if (slab_x > n || n % slab_x != 0) return GFFT_E_INVALID_ARG;
+    // sizes must stay addressable with 64-bit element offsets
+    const int64_t k = n / 2 + 1;
+    if (batch > (int64_t(1) << 62) / (slab_x * n * k * 2 * 8)) return GFFT_E_UNSUPPORTED;
+
+    int count = 0;
+    if (hipGetDeviceCount(&count) != hipSuccess || count < 1) return GFFT_E_NO_DEVICE;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return GFFT_E_HIP;
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, dev) != hipSuccess) return GFFT_E_HIP;
+    if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0) return GFFT_E_NO_DEVICE;
+
+    gfft_plan* p = new (std::nothrow) gfft_plan;
+    if (!p) return GFFT_E_NOMEM;
+    p->n = n;
+    p->x = slab_x;
+    p->p = n / slab_x;
+    p->y = n / p->p;
+    p->batch = batch;
+    p->k = k;
+    p->lg_n = ilog2(n);
+    p->lg_x = ilog2(slab_x);
+    p->lg_p = ilog2(p->p);
+    p->lg_y = ilog2(p->y);
+    p->dtype = dtype;
+    p->flags = flags;
+    p->device = dev;
+    p->tw = nullptr;
+
+    // FP64 twiddles, rounded once to the working precision.
+    const size_t bytes = size_t(n) * 2 * (dtype == GFFT_F64 ? 8 : 4);
+    std::vector<unsigned char> host(bytes);
+    for (int64_t m = 0; m < n; ++m) {
+        double re, im;
+        unit_root(m, n, &re, &im);
+        if (dtype == GFFT_F64) {
+            double* h = reinterpret_cast<double*>(host.data());
+            h[2 * m] = re;
+            h[2 * m + 1] = im;
+        } else {
+            float* h = reinterpret_cast<float*>(host.data());
+            h[2 * m] = float(re);
+            h[2 * m + 1] = float(im);
+        }
+    }
+    if (hipMalloc(&p->tw, bytes) != hipSuccess) {
+        delete p;
+        return GFFT_E_NOMEM;
+    }
+    if (hipMemcpy(p->tw, host.data(), bytes, hipMemcpyHostToDevice) != hipSuccess) {
+        (void)hipFree(p->tw);
+        delete p;
+        return GFFT_E_HIP;
+    }
+    *out = p;
+    return GFFT_OK;
+}
+
+gfft_status gfft_plan_destroy(gfft_plan* p) {
+    if (!p) return GFFT_OK;
+    gfft_status st = GFFT_OK;
+    if (p->tw && hipFree(p->tw) != hipSuccess) st = GFFT_E_HIP;
+    delete p;
+    return st;
+}
+
+gfft_status gfft_plan_query(const gfft_plan* p, gfft_plan_sizes* s) {
+    if (!p || !s) return GFFT_E_INVALID_ARG;
+    s->n = p->n;
+    s->slab_x = p->x;
+    s->ranks = p->p;
+    s->batch = p->batch;
+    s->k = p->k;
+    s->real_bytes = real_bytes(p);
+    s->complex_bytes = cplx_bytes(p);
+    s->pencil_bytes = p->batch * p->n * p->y * p->k * 2 * elt(p);
+    s->chunk_bytes = p->x * p->y * p->k * 2 * elt(p);
+    return GFFT_OK;
+}
+
+gfft_status gfft_exec_r2c(const gfft_plan* p, const void* in, void* out, void* stream) {
+    return forward(p, in, out, 1.0, false, stream);
+}
+
+gfft_status gfft_exec_c2r_adjoint(const gfft_plan* p, const void* in, void* out,
+                                  double scale, void* stream) {
+    return forward(p, in, out, scale, true, stream);
+}
+
+gfft_status gfft_exec_c2r(const gfft_plan* p, void* in, void* out, double scale,
+                          void* stream) {
+    return inverse(p, in, out, scale, false, stream);
+}
+
+gfft_status gfft_exec_r2c_adjoint(const gfft_plan* p, void* in, void* out, double scale,
+                                  void* stream) {
+    return inverse(p, in, out, scale, true, stream);
+}
+
+gfft_status gfft_pack_slab_for_alltoall(const gfft_plan* p, const void* src, void* dst,
+                                        void* stream) {
+    if (!p) return GFFT_E_INVALID_ARG;
+    gfft_status st = check_ptr(src);
+    if (st != GFFT_OK || (st = check_ptr(dst)) != GFFT_OK) return st;
+    if (overlap(src, cplx_bytes(p), dst, cplx_bytes(p))) return GFFT_E_INVALID_ARG;
+    return hip_status(gfft::launch_pack(f64(p), src, dst, p->batch * p->p * p->x, p->lg_x,
+                                        p->lg_p, p->n, p->y, p->k, true, as_stream(stream)));
+}
+
+gfft_status gfft_unpack_slab_from_alltoall(const gfft_plan* p, const void* src, void* dst,
+                                           void* stream) {
+    if (!p) return GFFT_E_INVALID_ARG;
+    gfft_status st = check_ptr(src);
+    if (st != GFFT_OK || (st = check_ptr(dst)) != GFFT_OK) return st;
+    if (overlap(src, cplx_bytes(p), dst, cplx_bytes(p))) return GFFT_E_INVALID_ARG;
+    return hip_status(gfft::launch_pack(f64(p), src, dst, p->batch * p->p * p->x, p->lg_x,
+                                        p->lg_p, p->n, p->y, p->k, false, as_stream(stream)));
+}
+
+gfft_status gfft_exec_x_c2c(const gfft_plan* p, void* pencil, int sign, void* stream) {
+    if (!p) return GFFT_E_INVALID_ARG;
+    if (sign != -1 && sign != 1) return GFFT_E_INVALID_ARG;
+    gfft_status st = check_ptr(pencil);
+    if (st != GFFT_OK) return st;
+    return run_x(p, pencil, sign, as_stream(stream));
+}
+
+gfft_status gfft_exec_z_r2c(const gfft_plan* p, const void* in, void* out, double scale,
+                            int weighted, void* stream) {
+    gfft_status st = check_r2c_args(p, in, out);
+    if (st != GFFT_OK) return st;
+    if (!std::isfinite(scale)) return GFFT_E_INVALID_ARG;
+    return run_z_r2c(p, in, out, scale, weighted != 0, as_stream(stream));
+}
+
+gfft_status gfft_exec_y_c2c(const gfft_plan* p, void* data, int sign, void* stream) {
+    if (!p) return GFFT_E_INVALID_ARG;
+    if (sign != -1 && sign != 1) return GFFT_E_INVALID_ARG;
+    gfft_status st = check_ptr(data);
+    if (st != GFFT_OK) return st;
+    return run_y(p, data, sign, as_stream(stream));
+}
+
+gfft_status gfft_exec_z_c2r(const gfft_plan* p, const void* in, void* out, double scale,
+                            int weighted, void* stream) {
+    gfft_status st = check_r2c_args(p, out, in);
+    if (st != GFFT_OK) return st;
+    if (!std::isfinite(scale)) return GFFT_E_INVALID_ARG;
+    return run_z_c2r(p, in, out, scale, weighted != 0, as_stream(stream));
+}
+
+}  // extern "C"

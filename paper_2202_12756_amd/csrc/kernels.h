@@ -1,0 +1,44 @@
+// Kernel launchers of the slab 3D real FFT (host-callable, C++ linkage).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace gfft {
+
+// Maps a natural row index r of the [batch][X][N] row space (one row = one
+// z-line) to the row it occupies in a half-spectrum buffer: the natural row
+// when lg_y == lg_n, or the all-to-all send order [p][X][N/p] of the slab's
+// chunks (chunk j = y / (N/p)) otherwise.  All extents are powers of two.
+struct row_map {
+    int lg_n, lg_x, lg_y;
+};
+
+// Address of element (b, n, m) of a batch of strided lines:
+//   (b >> lg_bx) * b_hi + (b & (2^lg_bx - 1)) * b_lo
+//   + (n >> lg_y) * s_hi + (n & (2^lg_y - 1)) * s_lo + m
+// which covers the y lines of a natural or send-ordered slab and the x
+// lines of a pencil.
+struct line_map {
+    int64_t b_hi, b_lo, s_hi, s_lo;
+    int lg_bx, lg_y;
+};
+
+// All launchers return hipSuccess or the launch error.
+// tw: device table of W_N^m = exp(-2 pi i m / N), m = 0..N-1, of type T.
+hipError_t launch_z_r2c(bool f64, int n, const void* in, void* out, const void* tw,
+                        int64_t rows, row_map map, double mul_edge, double mul_int,
+                        hipStream_t s);
+hipError_t launch_z_c2r(bool f64, int n, const void* in, void* out, const void* tw,
+                        int64_t rows, row_map map, double mul_edge, double mul_int,
+                        hipStream_t s);
+hipError_t launch_strided(bool f64, int n, int sign, void* data, const void* tw,
+                          int64_t m_cols, int64_t n_b, line_map lm, hipStream_t s);
+// Copy `chunks` runs of `len` complex values: run c = (bb, j, xl) goes from
+// natural offset bb*X*N*K + (xl*N + j*Y)*K to send offset
+// bb*X*N*K + (j*X + xl)*Y*K (to_send = true) or back (to_send = false).
+hipError_t launch_pack(bool f64, const void* src, void* dst, int64_t chunks,
+                       int lg_x, int lg_p, int64_t n, int64_t y, int64_t k,
+                       bool to_send, hipStream_t s);
+
+}  // namespace gfft

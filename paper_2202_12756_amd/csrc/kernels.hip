@@ -1,0 +1,317 @@
+// HIP kernels of the slab 3D real FFT for gfx950 (MI355X).
+//
+// Three pass kinds cover the whole path (section 3 steps 1 and 5 and their
+// inverse; steps 2-4 are row permutations folded into addressing):
+//   z pass  : contiguous rows.  A row of N reals is read as N/2 complex
+//             values z[n] = x[2n] + i x[2n+1], transformed with an N/2-point
+//             complex FFT, and split into the K = N/2+1 bins of the real
+//             transform (and the reverse for C2R).
+//   y/x pass: strided lines.  A workgroup owns TC adjacent columns of a
+//             batch of lines; lanes of consecutive columns read consecutive
+//             addresses, so every load and store is a contiguous run of
+//             TC complex values per line position.
+//   pack    : the send-order permutation as a plain copy of contiguous runs.
+// Memory bound: each pass reads and writes its array once.
+#include "cx.h"
+#include "engine.h"
+#include "kernels.h"
+
+namespace gfft {
+
+constexpr int kThreads = 256;
+
+__device__ __forceinline__ int64_t map_row(int64_t r, row_map m) {
+    const int64_t bx = r >> m.lg_n;
+    const int64_t y = r & ((int64_t(1) << m.lg_n) - 1);
+    const int64_t b = bx >> m.lg_x;
+    const int64_t xl = bx & ((int64_t(1) << m.lg_x) - 1);
+    const int64_t j = y >> m.lg_y;
+    const int64_t yl = y & ((int64_t(1) << m.lg_y) - 1);
+    return (b << (m.lg_x + m.lg_n)) + ((((j << m.lg_x) + xl)) << m.lg_y) + yl;
+}
+
+// Consecutive workgroup ids are dealt round-robin to the 8 XCDs, each with
+// its own L2.  Remap so that XCD x works through one contiguous range of
+// tiles: neighbouring tiles share cache lines at their edges.
+__device__ __forceinline__ int64_t xcd_tile(int64_t g, int64_t G) {
+    constexpr int kXcd = 8;
+    const int64_t per = G / kXcd;
+    if (g >= per * kXcd) return g;
+    return (g % kXcd) * per + g / kXcd;
+}
+
+template <int M>
+struct zshape {
+    static constexpr int E = M < 16 ? M : 16;     // elements per thread
+    static constexpr int TPT = M / E;             // threads per row
+    static constexpr int RPB = kThreads / TPT;    // rows per workgroup
+};
+
+// ---------------------------------------------------------------- z R2C
+template <typename T, int N>
+__global__ __launch_bounds__(kThreads) void k_z_r2c(
+    const T* __restrict__ in, cx<T>* __restrict__ out, const cx<T>* __restrict__ tw,
+    int64_t rows, row_map map, T mul_edge, T mul_int) {
+    constexpr int M = N / 2, K = M + 1;
+    using Z = zshape<M>;
+    constexpr int E = Z::E, TPT = Z::TPT, RPB = Z::RPB;
+    __shared__ cx<T> lds[RPB * M];
+
+    const int rl = threadIdx.x / TPT;
+    const int t = threadIdx.x % TPT;
+    const int64_t row = int64_t(blockIdx.x) * RPB + rl;
+    const bool valid = row < rows;
+
+    const cx<T>* src = reinterpret_cast<const cx<T>*>(in + row * N);
+    cx<T> a[E];
+#pragma unroll
+    for (int m = 0; m < E; ++m) a[m] = valid ? src[t + m * TPT] : cx<T>{T(0), T(0)};
+
+    const lds_rows<T> L{lds + rl * M};
+    fft_regs<T, M, E, -1>(a, t, tw, 2, L);
+
+    // Split Z = FFT_M(z) into the real transform:
+    //   X[k] = (Z[k] + conj Z[M-k])/2 - (i/2) W_N^k (Z[k] - conj Z[M-k]),
+    //   X[M] = Re Z[0] - Im Z[0].
+#pragma unroll
+    for (int m = 0; m < E; ++m) L.put(t + m * TPT, a[m]);
+    __syncthreads();
+    if (!valid) return;
+    cx<T>* dst = out + map_row(row, map) * K;
+#pragma unroll
+    for (int m = 0; m < E; ++m) {
+        const int k = t + m * TPT;
+        const cx<T> zk = a[m];
+        const cx<T> zc = conjg(L.get((M - k) & (M - 1)));
+        const cx<T> A = scal(zk + zc, T(0.5));
+        const cx<T> B = scal(zk - zc, T(0.5));
+        const cx<T> wb = cmul(tw[k], B);
+        const T f = k == 0 ? mul_edge : mul_int;
+        dst[k] = cx<T>{(A.x + wb.y) * f, (A.y - wb.x) * f};
+    }
+    if (t == 0) dst[M] = cx<T>{(a[0].x - a[0].y) * mul_edge, T(0)};
+}
+
+// ---------------------------------------------------------------- z C2R
+template <typename T, int N>
+__global__ __launch_bounds__(kThreads) void k_z_c2r(
+    const cx<T>* __restrict__ in, T* __restrict__ out, const cx<T>* __restrict__ tw,
+    int64_t rows, row_map map, T mul_edge, T mul_int) {
+    constexpr int M = N / 2, K = M + 1;
+    using Z = zshape<M>;
+    constexpr int E = Z::E, TPT = Z::TPT, RPB = Z::RPB;
+    __shared__ cx<T> lds[RPB * M];
+
+    const int rl = threadIdx.x / TPT;
+    const int t = threadIdx.x % TPT;
+    const int64_t row = int64_t(blockIdx.x) * RPB + rl;
+    const bool valid = row < rows;
+    const lds_rows<T> L{lds + rl * M};
+
+    // Load G[0..M-1] (registers and LDS) and G[M] (thread t = 0), dropping
+    // the imaginary parts of kz = 0 and kz = N/2 and applying the bin
+    // multipliers (scale, and 1/w for the adjoint).
+    cx<T> g[E];
+    cx<T> g_m{T(0), T(0)};
+    if (valid) {
+        const cx<T>* src = in + map_row(row, map) * K;
+#pragma unroll
+        for (int m = 0; m < E; ++m) g[m] = src[t + m * TPT];
+        if (t == 0) g_m = src[M];
+    } else {
+#pragma unroll
+        for (int m = 0; m < E; ++m) g[m] = cx<T>{T(0), T(0)};
+    }
+#pragma unroll
+    for (int m = 0; m < E; ++m) {
+        const int k = t + m * TPT;
+        if (k == 0) g[m] = cx<T>{g[m].x * mul_edge, T(0)};
+        else g[m] = scal(g[m], mul_int);
+        L.put(k, g[m]);
+    }
+    g_m = cx<T>{g_m.x * mul_edge, T(0)};
+    __syncthreads();
+
+    // Z'[k] = (G[k] + conj G[M-k]) + i conj(W_N^k) (G[k] - conj G[M-k]);
+    // its inverse M-point FFT interleaves the even and odd outputs.
+    cx<T> a[E];
+#pragma unroll
+    for (int m = 0; m < E; ++m) {
+        const int k = t + m * TPT;
+        const cx<T> gc = conjg(k == 0 ? g_m : L.get(M - k));
+        const cx<T> s = g[m] + gc;
+        const cx<T> d = cmulc(g[m] - gc, tw[k]);
+        a[m] = cx<T>{s.x - d.y, s.y + d.x};
+    }
+    __syncthreads();
+    fft_regs<T, M, E, +1>(a, t, tw, 2, L);
+    if (!valid) return;
+    cx<T>* dst = reinterpret_cast<cx<T>*>(out + row * N);
+#pragma unroll
+    for (int m = 0; m < E; ++m) dst[t + m * TPT] = a[m];
+}
+
+// ---------------------------------------------------------------- y / x C2C
+template <typename T, int N>
+struct sshape {
+    static constexpr int E = 16;
+    static constexpr int TPT = N / E;
+    // columns per tile: 256 threads, at most 64 KiB of LDS
+    static constexpr int TC_T = kThreads / TPT;
+    static constexpr int TC_L = 65536 / (N * int(sizeof(cx<T>)));
+    static constexpr int TC0 = TC_T < TC_L ? TC_T : TC_L;
+    static constexpr int TC = TC0 < 1 ? 1 : TC0;
+    static constexpr int THREADS = TC * TPT;
+};
+
+template <typename T, int N, int S>
+__global__ __launch_bounds__((sshape<T, N>::THREADS)) void k_strided(
+    cx<T>* __restrict__ data, const cx<T>* __restrict__ tw, int64_t m_cols,
+    int64_t tiles_m, line_map lm) {
+    using SH = sshape<T, N>;
+    constexpr int E = SH::E, TPT = SH::TPT, TC = SH::TC;
+    __shared__ cx<T> lds[N * TC];
+
+    const int c = threadIdx.x % TC;
+    const int t = threadIdx.x / TC;
+    const int64_t tile = xcd_tile(blockIdx.x, gridDim.x);
+    const int64_t b = tile / tiles_m;
+    const int64_t m = (tile - b * tiles_m) * TC + c;
+    const bool valid = m < m_cols;
+    const int64_t ymask = (int64_t(1) << lm.lg_y) - 1;
+    cx<T>* base = data + (b >> lm.lg_bx) * lm.b_hi +
+                  (b & ((int64_t(1) << lm.lg_bx) - 1)) * lm.b_lo + m;
+
+    cx<T> a[E];
+#pragma unroll
+    for (int i = 0; i < E; ++i) {
+        const int64_t n = t + i * TPT;
+        a[i] = valid ? base[(n >> lm.lg_y) * lm.s_hi + (n & ymask) * lm.s_lo]
+                     : cx<T>{T(0), T(0)};
+    }
+    fft_regs<T, N, E, S>(a, t, tw, 1, lds_cols<T, TC>{lds, c});
+    if (!valid) return;
+#pragma unroll
+    for (int i = 0; i < E; ++i) {
+        const int64_t n = t + i * TPT;
+        base[(n >> lm.lg_y) * lm.s_hi + (n & ymask) * lm.s_lo] = a[i];
+    }
+}
+
+// ---------------------------------------------------------------- pack
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_pack(
+    const cx<T>* __restrict__ src, cx<T>* __restrict__ dst, int64_t len,
+    int64_t blocks_per_chunk, int lg_x, int lg_p, int64_t n, int64_t y, int64_t k,
+    bool to_send) {
+    const int64_t chunk = blockIdx.x / blocks_per_chunk;
+    const int64_t part = blockIdx.x - chunk * blocks_per_chunk;
+    // chunk = (bb, j, xl) with xl fastest
+    const int64_t xl = chunk & ((int64_t(1) << lg_x) - 1);
+    const int64_t j = (chunk >> lg_x) & ((int64_t(1) << lg_p) - 1);
+    const int64_t bb = chunk >> (lg_x + lg_p);
+    const int64_t X = int64_t(1) << lg_x;
+    const int64_t plane = bb * X * n * k;
+    const int64_t nat = plane + (xl * n + j * y) * k;
+    const int64_t snd = plane + (j * X + xl) * y * k;
+    const cx<T>* s = src + (to_send ? nat : snd);
+    cx<T>* d = dst + (to_send ? snd : nat);
+    const int64_t step = blocks_per_chunk * kThreads;
+    for (int64_t e = part * kThreads + threadIdx.x; e < len; e += step) d[e] = s[e];
+}
+
+// ---------------------------------------------------------------- launchers
+template <typename T, int N>
+static hipError_t z_r2c_n(const void* in, void* out, const void* tw, int64_t rows,
+                          row_map map, double me, double mi, hipStream_t s) {
+    constexpr int RPB = zshape<N / 2>::RPB;
+    const int64_t blocks = (rows + RPB - 1) / RPB;
+    if (blocks == 0) return hipSuccess;
+    hipLaunchKernelGGL((k_z_r2c<T, N>), dim3(blocks), dim3(kThreads), 0, s,
+                       static_cast<const T*>(in), static_cast<cx<T>*>(out),
+                       static_cast<const cx<T>*>(tw), rows, map, T(me), T(mi));
+    return hipGetLastError();
+}
+
+template <typename T, int N>
+static hipError_t z_c2r_n(const void* in, void* out, const void* tw, int64_t rows,
+                          row_map map, double me, double mi, hipStream_t s) {
+    constexpr int RPB = zshape<N / 2>::RPB;
+    const int64_t blocks = (rows + RPB - 1) / RPB;
+    if (blocks == 0) return hipSuccess;
+    hipLaunchKernelGGL((k_z_c2r<T, N>), dim3(blocks), dim3(kThreads), 0, s,
+                       static_cast<const cx<T>*>(in), static_cast<T*>(out),
+                       static_cast<const cx<T>*>(tw), rows, map, T(me), T(mi));
+    return hipGetLastError();
+}
+
+template <typename T, int N>
+static hipError_t strided_n(int sign, void* data, const void* tw, int64_t m_cols,
+                            int64_t n_b, line_map lm, hipStream_t s) {
+    using SH = sshape<T, N>;
+    const int64_t tiles_m = (m_cols + SH::TC - 1) / SH::TC;
+    const int64_t blocks = tiles_m * n_b;
+    if (blocks == 0) return hipSuccess;
+    if (sign < 0)
+        hipLaunchKernelGGL((k_strided<T, N, -1>), dim3(blocks), dim3(SH::THREADS), 0, s,
+                           static_cast<cx<T>*>(data), static_cast<const cx<T>*>(tw),
+                           m_cols, tiles_m, lm);
+    else
+        hipLaunchKernelGGL((k_strided<T, N, +1>), dim3(blocks), dim3(SH::THREADS), 0, s,
+                           static_cast<cx<T>*>(data), static_cast<const cx<T>*>(tw),
+                           m_cols, tiles_m, lm);
+    return hipGetLastError();
+}
+
+#define GFFT_DISPATCH_N(FN, T, ...)                 \
+    switch (n) {                                    \
+        case 16: return FN<T, 16>(__VA_ARGS__);     \
+        case 32: return FN<T, 32>(__VA_ARGS__);     \
+        case 64: return FN<T, 64>(__VA_ARGS__);     \
+        case 128: return FN<T, 128>(__VA_ARGS__);   \
+        case 256: return FN<T, 256>(__VA_ARGS__);   \
+        case 512: return FN<T, 512>(__VA_ARGS__);   \
+        case 1024: return FN<T, 1024>(__VA_ARGS__); \
+        case 2048: return FN<T, 2048>(__VA_ARGS__); \
+        case 4096: return FN<T, 4096>(__VA_ARGS__); \
+        default: return hipErrorInvalidValue;       \
+    }
+
+hipError_t launch_z_r2c(bool f64, int n, const void* in, void* out, const void* tw,
+                        int64_t rows, row_map map, double me, double mi, hipStream_t s) {
+    if (f64) { GFFT_DISPATCH_N(z_r2c_n, double, in, out, tw, rows, map, me, mi, s) }
+    GFFT_DISPATCH_N(z_r2c_n, float, in, out, tw, rows, map, me, mi, s)
+}
+
+hipError_t launch_z_c2r(bool f64, int n, const void* in, void* out, const void* tw,
+                        int64_t rows, row_map map, double me, double mi, hipStream_t s) {
+    if (f64) { GFFT_DISPATCH_N(z_c2r_n, double, in, out, tw, rows, map, me, mi, s) }
+    GFFT_DISPATCH_N(z_c2r_n, float, in, out, tw, rows, map, me, mi, s)
+}
+
+hipError_t launch_strided(bool f64, int n, int sign, void* data, const void* tw,
+                          int64_t m_cols, int64_t n_b, line_map lm, hipStream_t s) {
+    if (f64) { GFFT_DISPATCH_N(strided_n, double, sign, data, tw, m_cols, n_b, lm, s) }
+    GFFT_DISPATCH_N(strided_n, float, sign, data, tw, m_cols, n_b, lm, s)
+}
+
+hipError_t launch_pack(bool f64, const void* src, void* dst, int64_t chunks, int lg_x,
+                       int lg_p, int64_t n, int64_t y, int64_t k, bool to_send,
+                       hipStream_t s) {
+    const int64_t len = y * k;
+    int64_t bpc = (len + kThreads * 4 - 1) / (kThreads * 4);
+    if (bpc < 1) bpc = 1;
+    const int64_t blocks = chunks * bpc;
+    if (blocks == 0 || len == 0) return hipSuccess;
+    if (f64)
+        hipLaunchKernelGGL((k_pack<double>), dim3(blocks), dim3(kThreads), 0, s,
+                           static_cast<const cx<double>*>(src), static_cast<cx<double>*>(dst),
+                           len, bpc, lg_x, lg_p, n, y, k, to_send);
+    else
+        hipLaunchKernelGGL((k_pack<float>), dim3(blocks), dim3(kThreads), 0, s,
+                           static_cast<const cx<float>*>(src), static_cast<cx<float>*>(dst),
+                           len, bpc, lg_x, lg_p, n, y, k, to_send);
+    return hipGetLastError();
+}
+
+}  // namespace gfft

@@ -1,0 +1,206 @@
+"""Torch-facing plan object over the C ABI.
+
+Torch supplies device memory and the stream; the wrapper checks shapes,
+dtypes, devices and contiguity (the C ABI cannot see buffer lengths), then
+passes raw device addresses and the current HIP stream to libgfft.so.
+"""
+from __future__ import annotations
+
+import torch
+
+from . import _lib
+
+_REAL = {torch.float64: _lib.GFFT_F64, torch.float32: _lib.GFFT_F32}
+_CPLX = {torch.float64: torch.complex128, torch.float32: torch.complex64}
+
+
+def _stream(device) -> int:
+    return torch.cuda.current_stream(device).cuda_stream
+
+
+class Plan:
+    """One GPU's share of an N^3 real FFT (full grid when slab_x == n).
+
+    Layouts (C order, z fastest): real [batch, X, N, N]; half spectrum
+    [batch, X, N, K] complex, or the send order [batch, p, X, N/p, K] when
+    ``fuse_pack``; x-pencil [batch, N, N/p, K].  For batch == 1 the leading
+    batch dimension may be omitted.
+    """
+
+    def __init__(self, n: int, dtype=torch.float64, slab_x: int | None = None,
+                 batch: int = 1, fuse_pack: bool = False, device=None):
+        if dtype not in _REAL:
+            raise TypeError("dtype must be torch.float64 or torch.float32")
+        self.n = int(n)
+        self.dtype = dtype
+        self.cdtype = _CPLX[dtype]
+        self.slab_x = int(slab_x if slab_x is not None else n)
+        self.batch = int(batch)
+        self.fuse_pack = bool(fuse_pack)
+        self.device = torch.device(device if device is not None else "cuda")
+        flags = _lib.GFFT_FUSE_PACK if fuse_pack else 0
+        with torch.cuda.device(self.device):
+            st, h = _lib.gfft_plan_create(self.n, _REAL[dtype], self.slab_x,
+                                          self.batch, flags)
+        _lib.check(st, "gfft_plan_create")
+        self._h = h
+        st, s = _lib.gfft_plan_query(h)
+        _lib.check(st, "gfft_plan_query")
+        self.k = s.k
+        self.ranks = s.ranks
+        self.sizes = {f: getattr(s, f) for f, _ in _lib.gfft_plan_sizes._fields_}
+
+    # ------------------------------------------------------------ shapes
+    @property
+    def real_shape(self):
+        return (self.batch, self.slab_x, self.n, self.n)
+
+    @property
+    def spectrum_shape(self):
+        if self.fuse_pack:
+            return (self.batch, self.ranks, self.slab_x, self.n // self.ranks,
+                    self.k)
+        return (self.batch, self.slab_x, self.n, self.k)
+
+    @property
+    def send_shape(self):
+        return (self.batch, self.ranks, self.slab_x, self.n // self.ranks,
+                self.k)
+
+    @property
+    def pencil_shape(self):
+        return (self.batch, self.n, self.n // self.ranks, self.k)
+
+    def _check(self, t: torch.Tensor, dtype, numel: int, what: str):
+        if not isinstance(t, torch.Tensor):
+            raise TypeError(f"{what} must be a torch.Tensor")
+        if t.dtype != dtype:
+            raise TypeError(f"{what} must have dtype {dtype}, got {t.dtype}")
+        if t.device != self.device and not (
+                t.device.type == "cuda" and self.device.index is None
+                and t.device.index == torch.cuda.current_device()):
+            raise ValueError(f"{what} must live on {self.device}")
+        if not t.is_contiguous():
+            raise ValueError(f"{what} must be contiguous")
+        if t.numel() != numel:
+            raise ValueError(f"{what} has {t.numel()} elements, plan needs {numel}")
+        return t.data_ptr()
+
+    def _nreal(self):
+        return self.batch * self.slab_x * self.n * self.n
+
+    def _ncplx(self):
+        return self.batch * self.slab_x * self.n * self.k
+
+    def _npencil(self):
+        return self.batch * self.n * (self.n // self.ranks) * self.k
+
+    def empty_real(self):
+        return torch.empty(self.real_shape, dtype=self.dtype, device=self.device)
+
+    def empty_spectrum(self):
+        return torch.empty(self.spectrum_shape, dtype=self.cdtype,
+                           device=self.device)
+
+    # ------------------------------------------------------------ transforms
+    def r2c(self, x: torch.Tensor, out: torch.Tensor | None = None):
+        out = self.empty_spectrum() if out is None else out
+        a = self._check(x, self.dtype, self._nreal(), "input")
+        b = self._check(out, self.cdtype, self._ncplx(), "output")
+        _lib.check(_lib.gfft_exec_r2c(self._h, a, b, _stream(self.device)),
+                   "gfft_exec_r2c")
+        return out
+
+    def c2r(self, g: torch.Tensor, out: torch.Tensor | None = None,
+            scale: float = 1.0):
+        """Inverse (clobbers ``g``)."""
+        out = self.empty_real() if out is None else out
+        a = self._check(g, self.cdtype, self._ncplx(), "input")
+        b = self._check(out, self.dtype, self._nreal(), "output")
+        _lib.check(_lib.gfft_exec_c2r(self._h, a, b, float(scale),
+                                      _stream(self.device)), "gfft_exec_c2r")
+        return out
+
+    def r2c_adjoint(self, g: torch.Tensor, out=None, scale: float = 1.0):
+        """scale * R2C^T(g) = scale * C2R(g / w) (clobbers ``g``)."""
+        out = self.empty_real() if out is None else out
+        a = self._check(g, self.cdtype, self._ncplx(), "input")
+        b = self._check(out, self.dtype, self._nreal(), "output")
+        _lib.check(_lib.gfft_exec_r2c_adjoint(self._h, a, b, float(scale),
+                                              _stream(self.device)),
+                   "gfft_exec_r2c_adjoint")
+        return out
+
+    def c2r_adjoint(self, h: torch.Tensor, out=None, scale: float = 1.0):
+        """scale * C2R^T(h) = scale * w * R2C(h)."""
+        out = self.empty_spectrum() if out is None else out
+        a = self._check(h, self.dtype, self._nreal(), "input")
+        b = self._check(out, self.cdtype, self._ncplx(), "output")
+        _lib.check(_lib.gfft_exec_c2r_adjoint(self._h, a, b, float(scale),
+                                              _stream(self.device)),
+                   "gfft_exec_c2r_adjoint")
+        return out
+
+    def pack(self, slab: torch.Tensor, out: torch.Tensor | None = None):
+        out = (torch.empty(self.send_shape, dtype=self.cdtype,
+                           device=self.device) if out is None else out)
+        a = self._check(slab, self.cdtype, self._ncplx(), "slab")
+        b = self._check(out, self.cdtype, self._ncplx(), "send")
+        _lib.check(_lib.gfft_pack_slab_for_alltoall(self._h, a, b,
+                                                    _stream(self.device)),
+                   "gfft_pack_slab_for_alltoall")
+        return out
+
+    def unpack(self, recv: torch.Tensor, out: torch.Tensor | None = None):
+        out = (torch.empty((self.batch, self.slab_x, self.n, self.k),
+                           dtype=self.cdtype, device=self.device)
+               if out is None else out)
+        a = self._check(recv, self.cdtype, self._ncplx(), "recv")
+        b = self._check(out, self.cdtype, self._ncplx(), "slab")
+        _lib.check(_lib.gfft_unpack_slab_from_alltoall(self._h, a, b,
+                                                       _stream(self.device)),
+                   "gfft_unpack_slab_from_alltoall")
+        return out
+
+    def x_c2c(self, pencil: torch.Tensor, sign: int):
+        a = self._check(pencil, self.cdtype, self._npencil(), "pencil")
+        _lib.check(_lib.gfft_exec_x_c2c(self._h, a, int(sign),
+                                        _stream(self.device)), "gfft_exec_x_c2c")
+        return pencil
+
+    # ------------------------------------------------------------ passes
+    def z_r2c(self, x, out=None, scale: float = 1.0, weighted: bool = False):
+        out = self.empty_spectrum() if out is None else out
+        a = self._check(x, self.dtype, self._nreal(), "input")
+        b = self._check(out, self.cdtype, self._ncplx(), "output")
+        _lib.check(_lib.gfft_exec_z_r2c(self._h, a, b, float(scale),
+                                        int(weighted), _stream(self.device)),
+                   "gfft_exec_z_r2c")
+        return out
+
+    def y_c2c(self, data, sign: int):
+        a = self._check(data, self.cdtype, self._ncplx(), "data")
+        _lib.check(_lib.gfft_exec_y_c2c(self._h, a, int(sign),
+                                        _stream(self.device)), "gfft_exec_y_c2c")
+        return data
+
+    def z_c2r(self, g, out=None, scale: float = 1.0, weighted: bool = False):
+        out = self.empty_real() if out is None else out
+        a = self._check(g, self.cdtype, self._ncplx(), "input")
+        b = self._check(out, self.dtype, self._nreal(), "output")
+        _lib.check(_lib.gfft_exec_z_c2r(self._h, a, b, float(scale),
+                                        int(weighted), _stream(self.device)),
+                   "gfft_exec_z_c2r")
+        return out
+
+    # ------------------------------------------------------------ lifetime
+    def close(self):
+        h, self._h = getattr(self, "_h", None), None
+        if h:
+            _lib.check(_lib.gfft_plan_destroy(h), "gfft_plan_destroy")
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

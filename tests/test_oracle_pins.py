@@ -131,7 +131,7 @@ def _eq5_golden(n):
             if not line:
                 continue
             parts = line.split()
-            if parts[0] == "roundtrip_maxabs_fp64":
+            if parts[0] == "roundtrip_maxrel_fp64":
                 tol = float(parts[1])
                 continue
             idx = tuple(n - int(p[2:]) if p.startswith("N-") else int(p)
@@ -140,7 +140,7 @@ def _eq5_golden(n):
     return bins, tol
 
 
-@pytest.mark.parametrize("n", [16, 32, 64])
+@pytest.mark.parametrize("n", [16, 32, 64, 128])
 def test_p4_paper_test_field(n):
     f = synth.paper_test_field(n)
     bins, tol = _eq5_golden(n)
@@ -150,7 +150,7 @@ def test_p4_paper_test_field(n):
     got = oracle.r2c3d(f) / n ** 3
     assert np.max(np.abs(got - ref)) <= 1e-15 * n
     back = oracle.c2r3d(oracle.r2c3d(f), n, 1.0 / n ** 3)
-    assert np.max(np.abs(back - f)) <= tol
+    assert np.max(np.abs(back - f)) <= tol * np.max(np.abs(f))
 
 
 # ---------------------------------------------------------------- identities

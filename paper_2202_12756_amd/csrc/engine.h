@@ -28,31 +28,77 @@ struct stage_radix {
     static constexpr int value = (N / L) >= E ? E : (N / L);
 };
 
-// LDS views.  `put`/`get` address element `pos` of the transform this
-// thread works on.
-//   column tile: element (pos, c) at buf[pos*TC + c]      (strided axes)
-//   row tile:    element (row, pos) at buf[row*RS + pos]   (contiguous rows)
-template <typename T, int TC>
-struct lds_cols {
-    cx<T>* buf;
+// Where element `pos` of this thread's transform lives in an LDS buffer.
+//   columns: TC transforms side by side, element (pos, c) at pos*TC + c
+//   rows:    one transform per row, element pos at off + pos
+template <int TC>
+struct idx_cols {
     int c;
-    __device__ __forceinline__ void put(int pos, cx<T> v) const { buf[pos * TC + c] = v; }
-    __device__ __forceinline__ cx<T> get(int pos) const { return buf[pos * TC + c]; }
+    __device__ __forceinline__ int operator()(int pos) const { return pos * TC + c; }
+};
+struct idx_rows {
+    int off;
+    __device__ __forceinline__ int operator()(int pos) const { return off + pos; }
 };
 
-template <typename T>
-struct lds_rows {
-    cx<T>* buf;  // already offset to this thread's row
-    __device__ __forceinline__ void put(int pos, cx<T> v) const { buf[pos] = v; }
-    __device__ __forceinline__ cx<T> get(int pos) const { return buf[pos]; }
+// Exchange after a stage: every output slot q + r*NB goes to position
+// (j - k) R + k + r L; then slot m is reloaded from position t + m*TPT.
+template <int N, int E, int L, int R>
+struct xgeom {
+    static constexpr int NB = E / R, TPT = N / E;
+    __device__ __forceinline__ static int out_pos(int t, int s) {
+        const int q = s % NB, r = s / NB;
+        const int j = t + q * TPT, k = j & (L - 1);
+        return (j - k) * R + k + r * L;
+    }
+};
+
+// Whole complex values through a buffer of N*width complex entries.
+template <typename T, class Idx>
+struct xch_full {
+    cx<T>* buf;
+    Idx idx;
+    template <int N, int E, int L, int R>
+    __device__ __forceinline__ void run(cx<T> (&a)[E], int t) const {
+        using G = xgeom<N, E, L, R>;
+#pragma unroll
+        for (int s = 0; s < E; ++s) buf[idx(G::out_pos(t, s))] = a[s];
+        __syncthreads();
+#pragma unroll
+        for (int m = 0; m < E; ++m) a[m] = buf[idx(t + m * G::TPT)];
+        __syncthreads();
+    }
+};
+
+// Real parts, then imaginary parts, through a buffer of half the size.
+template <typename T, class Idx>
+struct xch_split {
+    T* buf;
+    Idx idx;
+    template <int N, int E, int L, int R>
+    __device__ __forceinline__ void run(cx<T> (&a)[E], int t) const {
+        using G = xgeom<N, E, L, R>;
+#pragma unroll
+        for (int s = 0; s < E; ++s) buf[idx(G::out_pos(t, s))] = a[s].x;
+        __syncthreads();
+#pragma unroll
+        for (int m = 0; m < E; ++m) a[m].x = buf[idx(t + m * G::TPT)];
+        __syncthreads();
+#pragma unroll
+        for (int s = 0; s < E; ++s) buf[idx(G::out_pos(t, s))] = a[s].y;
+        __syncthreads();
+#pragma unroll
+        for (int m = 0; m < E; ++m) a[m].y = buf[idx(t + m * G::TPT)];
+        __syncthreads();
+    }
 };
 
 // Run the stages from span L to the end.  `tw` is a table of
 // W_Ntab^m (m = 0..Ntab-1) with Ntab = N * tws; entry idx*tws is W_N^idx.
-template <typename T, int N, int E, int S, int L, class Lds>
+template <typename T, int N, int E, int S, int L, class X>
 __device__ __forceinline__ void fft_from(cx<T> (&a)[E], int t,
                                          const cx<T>* __restrict__ tw, int tws,
-                                         const Lds& lds) {
+                                         const X& xch) {
     constexpr int R = stage_radix<N, E, L>::value;
     constexpr int NB = E / R;       // butterflies per thread
     constexpr int TPT = N / E;      // threads per transform
@@ -74,29 +120,20 @@ __device__ __forceinline__ void fft_from(cx<T> (&a)[E], int t,
             }
         }
         dft<R, S>(b);
-        if constexpr (LAST) {
 #pragma unroll
-            for (int r = 0; r < R; ++r) a[q + r * NB] = b[r];
-        } else {
-            const int base = (j - k) * R + k;
-#pragma unroll
-            for (int r = 0; r < R; ++r) lds.put(base + r * L, b[r]);
-        }
+        for (int r = 0; r < R; ++r) a[q + r * NB] = b[r];
     }
     if constexpr (!LAST) {
-        __syncthreads();
-#pragma unroll
-        for (int m = 0; m < E; ++m) a[m] = lds.get(t + m * TPT);
-        __syncthreads();
-        fft_from<T, N, E, S, L * R>(a, t, tw, tws, lds);
+        xch.template run<N, E, L, R>(a, t);
+        fft_from<T, N, E, S, L * R>(a, t, tw, tws, xch);
     }
 }
 
-template <typename T, int N, int E, int S, class Lds>
+template <typename T, int N, int E, int S, class X>
 __device__ __forceinline__ void fft_regs(cx<T> (&a)[E], int t,
                                          const cx<T>* __restrict__ tw, int tws,
-                                         const Lds& lds) {
-    fft_from<T, N, E, S, 1>(a, t, tw, tws, lds);
+                                         const X& xch) {
+    fft_from<T, N, E, S, 1>(a, t, tw, tws, xch);
 }
 
 }  // namespace gfft

@@ -131,12 +131,12 @@ gfft_status run_z_c2r(const gfft_plan* p, const void* in, void* out, double scal
 }
 
 gfft_status run_y(const gfft_plan* p, void* data, int sign, hipStream_t s) {
-    return hip_status(gfft::launch_strided(f64(p), int(p->n), sign, data, p->tw, p->k,
+    return hip_status(gfft::launch_strided(f64(p), int(p->n), 0, sign, data, p->tw, p->k,
                                            p->batch * p->x, ymap(p), s));
 }
 
 gfft_status run_x(const gfft_plan* p, void* data, int sign, hipStream_t s) {
-    return hip_status(gfft::launch_strided(f64(p), int(p->n), sign, data, p->tw,
+    return hip_status(gfft::launch_strided(f64(p), int(p->n), 1, sign, data, p->tw,
                                            p->y * p->k, p->batch, xmap(p), s));
 }
 

@@ -32,7 +32,9 @@ hipError_t launch_z_r2c(bool f64, int n, const void* in, void* out, const void* 
 hipError_t launch_z_c2r(bool f64, int n, const void* in, void* out, const void* tw,
                         int64_t rows, row_map map, double mul_edge, double mul_int,
                         hipStream_t s);
-hipError_t launch_strided(bool f64, int n, int sign, void* data, const void* tw,
+// axis 0: y lines (short stride); axis 1: x lines (long stride).  Picks the
+// tile shape measured best for that stride.
+hipError_t launch_strided(bool f64, int n, int axis, int sign, void* data, const void* tw,
                           int64_t m_cols, int64_t n_b, line_map lm, hipStream_t s);
 // Copy `chunks` runs of `len` complex values: run c = (bb, j, xl) goes from
 // natural offset bb*X*N*K + (xl*N + j*Y)*K to send offset

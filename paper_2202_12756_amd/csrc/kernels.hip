@@ -67,14 +67,14 @@ __global__ __launch_bounds__(kThreads) void k_z_r2c(
 #pragma unroll
     for (int m = 0; m < E; ++m) a[m] = valid ? src[t + m * TPT] : cx<T>{T(0), T(0)};
 
-    const lds_rows<T> L{lds + rl * M};
-    fft_regs<T, M, E, -1>(a, t, tw, 2, L);
+    cx<T>* L = lds + rl * M;
+    fft_regs<T, M, E, -1>(a, t, tw, 2, xch_full<T, idx_rows>{lds, idx_rows{rl * M}});
 
     // Split Z = FFT_M(z) into the real transform:
     //   X[k] = (Z[k] + conj Z[M-k])/2 - (i/2) W_N^k (Z[k] - conj Z[M-k]),
     //   X[M] = Re Z[0] - Im Z[0].
 #pragma unroll
-    for (int m = 0; m < E; ++m) L.put(t + m * TPT, a[m]);
+    for (int m = 0; m < E; ++m) L[t + m * TPT] = a[m];
     __syncthreads();
     if (!valid) return;
     cx<T>* dst = out + map_row(row, map) * K;
@@ -82,7 +82,7 @@ __global__ __launch_bounds__(kThreads) void k_z_r2c(
     for (int m = 0; m < E; ++m) {
         const int k = t + m * TPT;
         const cx<T> zk = a[m];
-        const cx<T> zc = conjg(L.get((M - k) & (M - 1)));
+        const cx<T> zc = conjg(L[(M - k) & (M - 1)]);
         const cx<T> A = scal(zk + zc, T(0.5));
         const cx<T> B = scal(zk - zc, T(0.5));
         const cx<T> wb = cmul(tw[k], B);
@@ -106,7 +106,7 @@ __global__ __launch_bounds__(kThreads) void k_z_c2r(
     const int t = threadIdx.x % TPT;
     const int64_t row = int64_t(blockIdx.x) * RPB + rl;
     const bool valid = row < rows;
-    const lds_rows<T> L{lds + rl * M};
+    cx<T>* L = lds + rl * M;
 
     // Load G[0..M-1] (registers and LDS) and G[M] (thread t = 0), dropping
     // the imaginary parts of kz = 0 and kz = N/2 and applying the bin
@@ -127,7 +127,7 @@ __global__ __launch_bounds__(kThreads) void k_z_c2r(
         const int k = t + m * TPT;
         if (k == 0) g[m] = cx<T>{g[m].x * mul_edge, T(0)};
         else g[m] = scal(g[m], mul_int);
-        L.put(k, g[m]);
+        L[k] = g[m];
     }
     g_m = cx<T>{g_m.x * mul_edge, T(0)};
     __syncthreads();
@@ -138,13 +138,13 @@ __global__ __launch_bounds__(kThreads) void k_z_c2r(
 #pragma unroll
     for (int m = 0; m < E; ++m) {
         const int k = t + m * TPT;
-        const cx<T> gc = conjg(k == 0 ? g_m : L.get(M - k));
+        const cx<T> gc = conjg(k == 0 ? g_m : L[M - k]);
         const cx<T> s = g[m] + gc;
         const cx<T> d = cmulc(g[m] - gc, tw[k]);
         a[m] = cx<T>{s.x - d.y, s.y + d.x};
     }
     __syncthreads();
-    fft_regs<T, M, E, +1>(a, t, tw, 2, L);
+    fft_regs<T, M, E, +1>(a, t, tw, 2, xch_full<T, idx_rows>{lds, idx_rows{rl * M}});
     if (!valid) return;
     cx<T>* dst = reinterpret_cast<cx<T>*>(out + row * N);
 #pragma unroll
@@ -152,25 +152,38 @@ __global__ __launch_bounds__(kThreads) void k_z_c2r(
 }
 
 // ---------------------------------------------------------------- y / x C2C
-template <typename T, int N>
+// Tile shape of the strided pass: TC columns of length N per workgroup,
+// E = 16 elements per thread (TPT = N/16 threads per column), exchanges
+// through LDS either as whole complex values or split into real and
+// imaginary halves (half the LDS per tile, twice the barriers).
+//   AX = 0 (y lines, rows K apart): up to 1024 threads and 128 KiB of LDS,
+//          one wide tile per CU; measured best for short strides.
+//   AX = 1 (x lines, rows megabytes apart): up to 512 threads and 64 KiB,
+//          two tiles per CU (N <= 1024; longer lines use the AX = 0 shape).
+// TC is at most 16 columns (256 B runs in FP64) unless the lines are so
+// short that 256 threads need more.
+template <typename T, int N, int AX>
 struct sshape {
     static constexpr int E = 16;
     static constexpr int TPT = N / E;
-    // columns per tile: 256 threads, at most 64 KiB of LDS
-    static constexpr int TC_T = kThreads / TPT;
-    static constexpr int TC_L = 65536 / (N * int(sizeof(cx<T>)));
-    static constexpr int TC0 = TC_T < TC_L ? TC_T : TC_L;
-    static constexpr int TC = TC0 < 1 ? 1 : TC0;
-    static constexpr int THREADS = TC * TPT;
+    static constexpr bool WIDE = AX == 0 || N >= 2048;
+    static constexpr int MAXT = WIDE ? 1024 : 512;
+    static constexpr int LDS = WIDE ? 131072 : 65536;
+    static constexpr int TC_T = MAXT / TPT;
+    static constexpr int CAP = (256 / TPT) > 16 ? (256 / TPT) : 16;
+    static constexpr int FULL = LDS / (N * int(sizeof(cx<T>)));
+    static constexpr int A0 = TC_T < CAP ? TC_T : CAP;
+    static constexpr int A1 = A0 < 2 * FULL ? A0 : 2 * FULL;
+    static constexpr int TC = A1 < 1 ? 1 : A1;
+    static constexpr bool SPLIT = TC > FULL;
 };
 
-template <typename T, int N, int S>
-__global__ __launch_bounds__((sshape<T, N>::THREADS)) void k_strided(
+template <typename T, int N, int TC, bool SPLIT, int S>
+__global__ __launch_bounds__(TC * N / 16) void k_strided(
     cx<T>* __restrict__ data, const cx<T>* __restrict__ tw, int64_t m_cols,
     int64_t tiles_m, line_map lm) {
-    using SH = sshape<T, N>;
-    constexpr int E = SH::E, TPT = SH::TPT, TC = SH::TC;
-    __shared__ cx<T> lds[N * TC];
+    constexpr int E = 16, TPT = N / E;
+    __shared__ cx<T> lds[SPLIT ? (N * TC + 1) / 2 : N * TC];
 
     const int c = threadIdx.x % TC;
     const int t = threadIdx.x / TC;
@@ -189,7 +202,11 @@ __global__ __launch_bounds__((sshape<T, N>::THREADS)) void k_strided(
         a[i] = valid ? base[(n >> lm.lg_y) * lm.s_hi + (n & ymask) * lm.s_lo]
                      : cx<T>{T(0), T(0)};
     }
-    fft_regs<T, N, E, S>(a, t, tw, 1, lds_cols<T, TC>{lds, c});
+    if constexpr (SPLIT)
+        fft_regs<T, N, E, S>(a, t, tw, 1,
+                             xch_split<T, idx_cols<TC>>{reinterpret_cast<T*>(lds), {c}});
+    else
+        fft_regs<T, N, E, S>(a, t, tw, 1, xch_full<T, idx_cols<TC>>{lds, {c}});
     if (!valid) return;
 #pragma unroll
     for (int i = 0; i < E; ++i) {
@@ -245,22 +262,31 @@ static hipError_t z_c2r_n(const void* in, void* out, const void* tw, int64_t row
     return hipGetLastError();
 }
 
-template <typename T, int N>
-static hipError_t strided_n(int sign, void* data, const void* tw, int64_t m_cols,
-                            int64_t n_b, line_map lm, hipStream_t s) {
-    using SH = sshape<T, N>;
-    const int64_t tiles_m = (m_cols + SH::TC - 1) / SH::TC;
+template <typename T, int N, int AX>
+static hipError_t strided_ax(int sign, void* data, const void* tw, int64_t m_cols,
+                             int64_t n_b, line_map lm, hipStream_t s) {
+    using SH = sshape<T, N, AX>;
+    constexpr int TC = SH::TC;
+    const int64_t tiles_m = (m_cols + TC - 1) / TC;
     const int64_t blocks = tiles_m * n_b;
     if (blocks == 0) return hipSuccess;
+    const dim3 threads(TC * SH::TPT);
     if (sign < 0)
-        hipLaunchKernelGGL((k_strided<T, N, -1>), dim3(blocks), dim3(SH::THREADS), 0, s,
+        hipLaunchKernelGGL((k_strided<T, N, TC, SH::SPLIT, -1>), dim3(blocks), threads, 0, s,
                            static_cast<cx<T>*>(data), static_cast<const cx<T>*>(tw),
                            m_cols, tiles_m, lm);
     else
-        hipLaunchKernelGGL((k_strided<T, N, +1>), dim3(blocks), dim3(SH::THREADS), 0, s,
+        hipLaunchKernelGGL((k_strided<T, N, TC, SH::SPLIT, +1>), dim3(blocks), threads, 0, s,
                            static_cast<cx<T>*>(data), static_cast<const cx<T>*>(tw),
                            m_cols, tiles_m, lm);
     return hipGetLastError();
+}
+
+template <typename T, int N>
+static hipError_t strided_n(int axis, int sign, void* data, const void* tw, int64_t m_cols,
+                            int64_t n_b, line_map lm, hipStream_t s) {
+    if (axis == 0) return strided_ax<T, N, 0>(sign, data, tw, m_cols, n_b, lm, s);
+    return strided_ax<T, N, 1>(sign, data, tw, m_cols, n_b, lm, s);
 }
 
 #define GFFT_DISPATCH_N(FN, T, ...)                 \
@@ -289,10 +315,10 @@ hipError_t launch_z_c2r(bool f64, int n, const void* in, void* out, const void* 
     GFFT_DISPATCH_N(z_c2r_n, float, in, out, tw, rows, map, me, mi, s)
 }
 
-hipError_t launch_strided(bool f64, int n, int sign, void* data, const void* tw,
+hipError_t launch_strided(bool f64, int n, int axis, int sign, void* data, const void* tw,
                           int64_t m_cols, int64_t n_b, line_map lm, hipStream_t s) {
-    if (f64) { GFFT_DISPATCH_N(strided_n, double, sign, data, tw, m_cols, n_b, lm, s) }
-    GFFT_DISPATCH_N(strided_n, float, sign, data, tw, m_cols, n_b, lm, s)
+    if (f64) { GFFT_DISPATCH_N(strided_n, double, axis, sign, data, tw, m_cols, n_b, lm, s) }
+    GFFT_DISPATCH_N(strided_n, float, axis, sign, data, tw, m_cols, n_b, lm, s)
 }
 
 hipError_t launch_pack(bool f64, const void* src, void* dst, int64_t chunks, int lg_x,

@@ -34,7 +34,9 @@ def parse():
     ap.add_argument("--dtype", choices=["f64", "f32"], default="f64")
     ap.add_argument("--seed", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-planes", type=int, default=256,
+    ap.add_argument("--no-variants", action="store_true",
+                    help="skip the FP32 and adjoint lines")
+    ap.add_argument("--cpu-planes", type=int, default=512,
                     help="x-planes (and pencil columns) in the oracle sample")
     ap.add_argument("--traffic", default=None,
                     help="JSON file with per-kernel HBM bytes from rocprofv3")
@@ -46,7 +48,7 @@ def gflop_pair(n: int) -> float:
     return 2 * 5.0 * (n ** 3 / 2) * math.log2(n ** 3) / 1e9
 
 
-def cpu_baseline(n: int, planes: int, seed: int) -> dict:
+def cpu_baseline(n: int, planes: int, seed: int, min_seconds: float = 10.0) -> dict:
     """Time the FP64 oracle on a bounded sample of the same workload.
 
     Sample: the forward 2D R2C (z and y lines) and its inverse on `planes`
@@ -64,21 +66,85 @@ def cpu_baseline(n: int, planes: int, seed: int) -> dict:
     f = synth.uniform((planes, n, n), seed, torch.float64).numpy()
     pen = (synth.uniform((n, planes, k), seed + 1, torch.float64).numpy()
            + 1j * synth.uniform((n, planes, k), seed + 2, torch.float64).numpy())
+    reps = 0
     t0 = time.perf_counter()
-    g = oracle.r2c2d_planes(f)
-    oracle.c2r2d_planes(g, n, 1.0 / n ** 3)
-    h = oracle.x_c2c(pen, -1)
-    oracle.x_c2c(h, +1)
-    dt = time.perf_counter() - t0
+    while True:
+        g = oracle.r2c2d_planes(f)
+        oracle.c2r2d_planes(g, n, 1.0 / n ** 3)
+        h = oracle.x_c2c(pen, -1)
+        oracle.x_c2c(h, +1)
+        reps += 1
+        dt = time.perf_counter() - t0
+        if dt >= min_seconds or reps >= 20:
+            break
     per_axis_pair = gflop_pair(n) / 3.0
-    work = per_axis_pair * (2 * planes / n + planes / n)
+    work = reps * per_axis_pair * (2 * planes / n + planes / n)
     return {"value": round(work / dt, 3), "unit": "GFLOP/s",
             "cores": oracle.num_threads(), "kind": "oracle",
             "sample": (f"radix-2 FP64 oracle: 2D R2C+C2R on {planes} of {n} "
                        f"x-planes and x-line C2C fwd+inv on a [{n}][{planes}][{k}] "
-                       f"pencil; {dt:.2f} s wall, rate = nominal flops of those "
+                       f"pencil, repeated {reps}x; {dt:.2f} s wall, rate = nominal flops of those "
                        f"lines / time"),
             "seconds": round(dt, 3)}
+
+
+def time_pairs(fn, steps: int, warmup: int) -> float:
+    """Average ms of fn() over `steps` calls (after `warmup`), HIP events."""
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    a = torch.cuda.Event(enable_timing=True)
+    b = torch.cuda.Event(enable_timing=True)
+    a.record()
+    for _ in range(steps):
+        fn()
+    b.record()
+    torch.cuda.synchronize()
+    return a.elapsed_time(b) / steps
+
+
+def variants(n: int, steps: int, x64: torch.Tensor, dev) -> dict:
+    """The FP32 round trip and the adjoint pair beside the FP64 line.
+
+    fp32: the same round trip on the FP32 values of the FP64 input.
+    adjoint_f64: the gradient pair of a loss through both transforms,
+    C2R^T (scale w R2C) then R2C^T (C2R(G/w)), on the FP64 input.
+    """
+    from paper_2202_12756_amd import Plan
+
+    out = {}
+    gflop = gflop_pair(n)
+    k = n // 2 + 1
+    # FP32 round trip
+    p32 = Plan(n, torch.float32, device=dev)
+    x32 = x64.float()
+    F32 = p32.empty_spectrum()
+    y32 = p32.empty_real()
+    ms = time_pairs(lambda: (p32.r2c(x32, F32), p32.c2r(F32, y32, 1.0 / n ** 3)),
+                    steps, 2)
+    err = (torch.linalg.vector_norm(y32.double() - x64)
+           / torch.linalg.vector_norm(x64)).item()
+    R, C = n ** 3 * 4, n * n * k * 8
+    out["fp32"] = {"ms_per_pair": round(ms, 4), "GFLOPs": round(gflop / (ms * 1e-3), 2),
+                   "pair_hbm_roofline_frac": round(2 * (R + 5 * C) / (ms * 1e-3) / 1e9
+                                                   / PEAK_HBM_GBS, 4),
+                   "roundtrip_rel_l2_vs_fp64_input": err}
+    del x32, F32, y32, p32
+    torch.cuda.empty_cache()
+    # adjoint pair in FP64
+    p64 = Plan(n, torch.float64, device=dev)
+    G = p64.empty_spectrum()
+    h = p64.empty_real()
+    ms = time_pairs(lambda: (p64.c2r_adjoint(x64, G, 1.0 / n ** 3),
+                             p64.r2c_adjoint(G, h, 1.0)), steps, 2)
+    R, C = n ** 3 * 8, n * n * k * 16
+    out["adjoint_f64"] = {"ms_per_pair": round(ms, 4),
+                          "GFLOPs": round(gflop / (ms * 1e-3), 2),
+                          "pair_hbm_roofline_frac": round(2 * (R + 5 * C) / (ms * 1e-3)
+                                                          / 1e9 / PEAK_HBM_GBS, 4)}
+    del G, h, p64
+    torch.cuda.empty_cache()
+    return out
 
 
 def main():
@@ -213,6 +279,13 @@ def main():
         "roundtrip_maxabs": err,
         "roundtrip_rel_l2": rel,
     }
+    # achievable bandwidth: an 8.6 GB device-to-device copy
+    ms_copy = time_pairs(lambda: y.copy_(x), 5, 1)
+    line["copy_GBps"] = round(2 * R / (ms_copy * 1e-3) / 1e9, 1)
+    line["roofline"]["frac_of_copy"] = round(gbs[dom] / line["copy_GBps"], 4)
+    if not args.no_variants:
+        line["variants"] = variants(n, args.steps, x if dtype == torch.float64
+                                    else x.double(), dev)
     if not args.no_cpu_baseline:
         print("[bench] timing the CPU oracle sample", file=sys.stderr, flush=True)
         line["cpu_baseline"] = cpu_baseline(n, args.cpu_planes, args.seed)

@@ -1,0 +1,219 @@
+"""GPU parity at the benchmark workloads' own shapes.
+
+c1  64^3 FP64 uniform: every bin against both oracle methods.
+c2  512^3 Kolmogorov-spectrum field, FP64 and FP32: every bin.
+c3  1024^3 FP64 uniform (the benchmark workload, same launches): whole
+    kz-planes sampled from the oracle, plus the round trip.
+c4  rank 0's slab of a 4096^3 grid over 64 ranks: sampled planes of the
+    local 2D R2C in send order, the send blocks against the standalone pack
+    bit for bit, and sampled columns of the x pass on a received pencil.
+c5  8 x 256^3 FP32 fields: spectral-energy and Poisson losses through the
+    autograd wrappers against the FP64 oracle gradients and finite
+    differences.
+"""
+import gc
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import synth
+from helpers import TOL, host, rel_l2
+from paper_2202_12756_amd import Plan, irfft3, rfft3
+
+pytestmark = pytest.mark.gpu
+
+
+def _free():
+    gc.collect()
+    torch.cuda.empty_cache()
+
+
+def test_c1_64cubed_fp64_both_oracle_methods():
+    n = 64
+    p = Plan(n, torch.float64)
+    x = synth.uniform(p.real_shape, 1, torch.float64)
+    F = p.r2c(x.cuda())
+    back = p.c2r(F.clone(), scale=1.0 / n ** 3)
+    torch.cuda.synchronize()
+    f = x.numpy()[0]
+    for method in (oracle.DIRECT, oracle.RADIX2):
+        assert rel_l2(host(F)[0], oracle.r2c3d(f, method)) <= 1e-13
+    assert rel_l2(host(back)[0], f) <= 1e-13
+
+
+@pytest.fixture(scope="module")
+def kolmogorov_512():
+    n = 512
+    spec = synth.kolmogorov_half_spectrum(n, 2)
+    f = oracle.c2r3d(spec, n)
+    f /= np.sqrt(np.mean(f ** 2))
+    return f
+
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32], ids=["f64", "f32"])
+def test_c2_512cubed_kolmogorov(kolmogorov_512, dtype):
+    n = 512
+    f = kolmogorov_512
+    xin = torch.from_numpy(f).to(dtype)          # FP32: RNE of the FP64 field
+    fin = xin.double().numpy()                   # exact values the GPU sees
+    p = Plan(n, dtype)
+    F = p.r2c(xin.cuda().reshape(p.real_shape))
+    torch.cuda.synchronize()
+    Fh = host(F)[0]
+    ref = oracle.r2c3d(fin)
+    err = rel_l2(Fh, ref)
+    print(f"c2 512^3 {dtype}: forward rel-L2 vs FP64 oracle {err:.3e}")
+    assert err <= TOL[dtype]
+    del Fh, ref
+    back = p.c2r(F, scale=1.0 / n ** 3)
+    torch.cuda.synchronize()
+    rt = rel_l2(host(back)[0], fin)
+    print(f"c2 512^3 {dtype}: round trip rel-L2 {rt:.3e}")
+    assert rt <= TOL[dtype]
+    del F, back, p
+    _free()
+
+
+def test_c3_1024cubed_sampled_kz_planes_and_round_trip():
+    n = 1024
+    p = Plan(n, torch.float64)
+    x = synth.uniform(p.real_shape, 3, torch.float64, "cuda")
+    F = p.r2c(x)
+    kz = [0, 1, 257, 512]
+    Fs = host(F[0, :, :, kz])
+    torch.cuda.synchronize()
+    f = x[0].cpu().numpy()
+    ref = oracle.r2c3d_kz_planes(f, kz)
+    del f
+    err = rel_l2(Fs, ref)
+    print(f"c3 1024^3 sampled kz planes {kz}: rel-L2 {err:.3e}")
+    assert err <= 1e-13
+    y = p.c2r(F, scale=1.0 / n ** 3)
+    rt = (torch.linalg.vector_norm(y - x) / torch.linalg.vector_norm(x)).item()
+    print(f"c3 round trip rel-L2 {rt:.3e}")
+    assert rt <= 1e-13
+    del F, x, y, p
+    _free()
+
+
+def test_c4_4096_slab_share_of_64_ranks():
+    n, ranks = 4096, 64
+    X = n // ranks
+    k = n // 2 + 1
+    fused = Plan(n, torch.float64, slab_x=X, fuse_pack=True)
+    x = synth.uniform(fused.real_shape, 4, torch.float64, "cuda")  # rank 0: global index
+    send = fused.r2c(x)                                            # [1, 64, 64, 64, K]
+    torch.cuda.synchronize()
+    # sampled planes of the local 2D R2C, read out of the send blocks
+    planes = [0, 31, 63]
+    got = host(send[0][:, planes])                    # [64 chunks, 3, 64, K]
+    got = np.concatenate(list(got), axis=1)           # [3, N, K] (ky = j*64 + y_l)
+    src = np.stack([synth.uniform((n, n), 4, torch.float64, offset=pl * n * n).numpy()
+                    for pl in planes])
+    ref = oracle.r2c2d_planes(src)
+    err = rel_l2(got, ref)
+    print(f"c4 2D R2C on planes {planes}: rel-L2 {err:.3e}")
+    assert err <= 1e-13
+    del got, ref, src
+    # the fused send order is exactly the standalone pack of the natural result
+    plain = Plan(n, torch.float64, slab_x=X)
+    nat = plain.r2c(x)
+    packed = plain.pack(nat)
+    torch.cuda.synchronize()
+    assert torch.equal(packed, send)
+    del nat, packed, send, x, plain, fused
+    _free()
+    # x pass on a synthetic received pencil [4096][64][2049]
+    pen_plan = Plan(n, torch.float64, slab_x=X)
+    re = synth.uniform((n, X, k), 40, torch.float64, "cuda")
+    im = synth.uniform((n, X, k), 41, torch.float64, "cuda")
+    pen = torch.complex(re, im)
+    del re, im
+    cols = torch.from_numpy(np.random.Generator(np.random.PCG64(44)).choice(
+        X * k, size=512, replace=False))
+    before = host(pen.reshape(n, X * k)[:, cols.cuda()])
+    pen_plan.x_c2c(pen, -1)
+    after = host(pen.reshape(n, X * k)[:, cols.cuda()])
+    ref = oracle.c2c_axis(before, 0, -1)
+    err = rel_l2(after, ref)
+    print(f"c4 x pass on 512 sampled columns: rel-L2 {err:.3e}")
+    assert err <= 1e-13
+    del pen, pen_plan
+    _free()
+
+
+@pytest.fixture(scope="module")
+def c5_fields():
+    n, b = 256, 8
+    fs = []
+    for i in range(b):
+        f = oracle.c2r3d(synth.kolmogorov_half_spectrum(n, 5 + i), n)
+        fs.append((f / np.sqrt(np.mean(f ** 2))).astype(np.float32))
+    return np.stack(fs)
+
+
+def _energy_loss_gpu(u, plan, wk2):
+    F = rfft3(u, plan)
+    return torch.sum(wk2 * (F.real.double() ** 2 + F.imag.double() ** 2))
+
+
+def test_c5_energy_loss_gradient_fp32(c5_fields):
+    n, b = 256, 8
+    plan = Plan(n, torch.float32, batch=b)
+    wk2 = torch.from_numpy(oracle.half_weights(n) * oracle.k_squared(n)).cuda()
+    u = torch.from_numpy(c5_fields).cuda().reshape(plan.real_shape).requires_grad_(True)
+    L = _energy_loss_gpu(u, plan, wk2)
+    L.backward()
+    g = host(u.grad)
+    # FP64 oracle gradient per field, from the same (FP32) input values
+    errs = [rel_l2(g[i], oracle.energy_loss_grad(c5_fields[i].astype(np.float64)))
+            for i in range(b)]
+    print(f"c5 energy-loss gradient rel-L2 per field: max {max(errs):.3e}")
+    assert max(errs) <= TOL[torch.float32]
+    # central finite differences (eps = 1e-3) along seeded directions from the
+    # same spectral class as the fields: white-noise directions are nearly
+    # orthogonal to the smooth gradient, and an FP32 difference of two
+    # losses would then be rounding noise
+    eps = 1e-3
+    with torch.no_grad():
+        for s in range(4):
+            dir_np = np.stack([oracle.c2r3d(synth.kolmogorov_half_spectrum(n, 205 + 8 * s + i), n)
+                               for i in range(b)])
+            dir_np /= np.sqrt(np.mean(dir_np ** 2))
+            d = torch.from_numpy(dir_np.astype(np.float32)).cuda().reshape(plan.real_shape)
+            lp = _energy_loss_gpu(u + eps * d, plan, wk2).item()
+            lm = _energy_loss_gpu(u - eps * d, plan, wk2).item()
+            fd = (lp - lm) / (2 * eps)
+            an = torch.sum(u.grad.double() * d.double()).item()
+            assert abs(fd - an) <= 1e-3 * abs(an), (fd, an)
+    del u, plan
+    _free()
+
+
+def test_c5_poisson_loss_gradient_fp32(c5_fields):
+    n, b = 256, 8
+    plan = Plan(n, torch.float32, batch=b)
+    k2 = oracle.k_squared(n)
+    m = np.zeros_like(k2)
+    m[k2 > 0] = -1.0 / k2[k2 > 0]
+    mt = torch.from_numpy(m).to(torch.float32).cuda()
+    srcs = np.stack([synth.uniform((n, n, n), 105 + i, torch.float32).numpy()
+                     for i in range(b)])
+    f = torch.from_numpy(srcs).cuda().reshape(plan.real_shape).requires_grad_(True)
+    u = irfft3(mt * rfft3(f, plan), plan, 1.0 / n ** 3)
+    L = torch.sum(u.double() ** 2)
+    L.backward()
+    g = host(f.grad)
+    uh = host(u.detach())
+    errs_u, errs_g = [], []
+    for i in range(b):
+        fi = srcs[i].astype(np.float64)
+        errs_u.append(rel_l2(uh[i], oracle.poisson(fi)))
+        errs_g.append(rel_l2(g[i], oracle.poisson_loss_grad(fi)))
+    print(f"c5 Poisson: solution rel-L2 max {max(errs_u):.3e}, gradient max {max(errs_g):.3e}")
+    assert max(errs_u) <= TOL[torch.float32]
+    assert max(errs_g) <= TOL[torch.float32]
+    del f, u, plan
+    _free()

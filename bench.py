@@ -39,8 +39,46 @@ def parse():
     ap.add_argument("--cpu-planes", type=int, default=512,
                     help="x-planes (and pencil columns) in the oracle sample")
     ap.add_argument("--traffic", default=None,
-                    help="JSON file with per-kernel HBM bytes from rocprofv3")
+                    help="PMC traffic summary (default: the committed 1024^3 FP64 one)")
     return ap.parse_args()
+
+
+TRAFFIC_FILE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "profiles",
+                            "c3_1024_f64_pmc_traffic.md")
+
+
+def kernel_source_hash() -> str:
+    """Hash of the HIP sources, to tell whether recorded counters still apply."""
+    import glob
+    import hashlib
+
+    h = hashlib.sha256()
+    csrc = os.path.join(os.path.dirname(os.path.abspath(__file__)),
+                        "paper_2202_12756_amd", "csrc")
+    for f in sorted(glob.glob(os.path.join(csrc, "*"))):
+        h.update(os.path.basename(f).encode())
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def recorded_traffic(path: str, pass_name: str):
+    """Calibrated HBM bytes per launch of `pass_name` from the PMC summary,
+    or None when the summary is missing or the kernels changed since."""
+    if not os.path.exists(path):
+        return None
+    sha, rows = None, {}
+    with open(path) as fh:
+        for line in fh:
+            if line.startswith("kernel_source_sha256_16:"):
+                sha = line.split(":", 1)[1].strip()
+            elif line.startswith("| ") and not line.startswith("| pass"):
+                cells = [c.strip() for c in line.strip().strip("|").split("|")]
+                if len(cells) >= 5 and cells[4].isdigit():
+                    rows[cells[0]] = int(cells[4])
+    if sha != kernel_source_hash():
+        return None
+    return rows.get(pass_name)
 
 
 def gflop_pair(n: int) -> float:
@@ -238,9 +276,8 @@ def main():
     gbs = {p: bytes_pass[p] / (per_pass[p] * 1e-3) / 1e9 for p in passes}
     dom = max(passes, key=lambda p: per_pass[p])
     traffic = None
-    if args.traffic and os.path.exists(args.traffic):
-        with open(args.traffic) as fh:
-            traffic = json.load(fh).get(dom)
+    if n == 1024 and dtype == torch.float64:
+        traffic = recorded_traffic(args.traffic or TRAFFIC_FILE, dom)
 
     gflop = gflop_pair(n)
     model_bytes = 2 * (R + 5 * C)

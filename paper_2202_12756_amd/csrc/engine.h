@@ -21,11 +21,13 @@
 
 namespace gfft {
 
-// Radix of the stage that starts at span L: E while the remaining length
-// allows, then whatever is left (N, E powers of two).
+// Radix of the stage that starts at span L: min(E, 16) while the remaining
+// length allows, then whatever is left (N, E powers of two).  With E > 16 a
+// thread runs E/16 radix-16 butterflies per stage.
 template <int N, int E, int L>
 struct stage_radix {
-    static constexpr int value = (N / L) >= E ? E : (N / L);
+    static constexpr int RMAX = E < 16 ? E : 16;
+    static constexpr int value = (N / L) >= RMAX ? RMAX : (N / L);
 };
 
 // Where element `pos` of this thread's transform lives in an LDS buffer.

@@ -40,20 +40,30 @@ __device__ __forceinline__ int64_t xcd_tile(int64_t g, int64_t G) {
     return (g % kXcd) * per + g / kXcd;
 }
 
-template <int M>
+template <int M, int EMAX = 16, int THREADS = kThreads>
 struct zshape {
-    static constexpr int E = M < 16 ? M : 16;     // elements per thread
-    static constexpr int TPT = M / E;             // threads per row
-    static constexpr int RPB = kThreads / TPT;    // rows per workgroup
+    static constexpr int E = M < EMAX ? M : EMAX;  // elements per thread
+    static constexpr int TPT = M / E;              // threads per row
+    static constexpr int NT = THREADS > TPT ? THREADS : TPT;
+    static constexpr int RPB = NT / TPT;           // rows per workgroup
+};
+
+// Workgroup shape of the z passes, chosen by measurement at 1024^3:
+// FP64 R2C 8 elements per thread in 256-thread workgroups, FP64 C2R 16 per
+// thread in 64-thread workgroups, FP32 32 per thread in 64-thread ones.
+template <typename T, bool FWD>
+struct zcfg {
+    static constexpr int EMAX = sizeof(T) == 8 ? (FWD ? 8 : 16) : 32;
+    static constexpr int THREADS = sizeof(T) == 8 && FWD ? 256 : 64;
 };
 
 // ---------------------------------------------------------------- z R2C
-template <typename T, int N>
-__global__ __launch_bounds__(kThreads) void k_z_r2c(
+template <typename T, int N, int EMAX = 16, int THREADS = kThreads>
+__global__ __launch_bounds__((zshape<N / 2, EMAX, THREADS>::NT)) void k_z_r2c(
     const T* __restrict__ in, cx<T>* __restrict__ out, const cx<T>* __restrict__ tw,
     int64_t rows, row_map map, T mul_edge, T mul_int) {
     constexpr int M = N / 2, K = M + 1;
-    using Z = zshape<M>;
+    using Z = zshape<M, EMAX, THREADS>;
     constexpr int E = Z::E, TPT = Z::TPT, RPB = Z::RPB;
     __shared__ cx<T> lds[RPB * M];
 
@@ -93,12 +103,12 @@ __global__ __launch_bounds__(kThreads) void k_z_r2c(
 }
 
 // ---------------------------------------------------------------- z C2R
-template <typename T, int N>
-__global__ __launch_bounds__(kThreads) void k_z_c2r(
+template <typename T, int N, int EMAX = 16, int THREADS = kThreads>
+__global__ __launch_bounds__((zshape<N / 2, EMAX, THREADS>::NT)) void k_z_c2r(
     const cx<T>* __restrict__ in, T* __restrict__ out, const cx<T>* __restrict__ tw,
     int64_t rows, row_map map, T mul_edge, T mul_int) {
     constexpr int M = N / 2, K = M + 1;
-    using Z = zshape<M>;
+    using Z = zshape<M, EMAX, THREADS>;
     constexpr int E = Z::E, TPT = Z::TPT, RPB = Z::RPB;
     __shared__ cx<T> lds[RPB * M];
 
@@ -152,23 +162,24 @@ __global__ __launch_bounds__(kThreads) void k_z_c2r(
 }
 
 // ---------------------------------------------------------------- y / x C2C
-// Tile shape of the strided pass: TC columns of length N per workgroup,
-// E = 16 elements per thread (TPT = N/16 threads per column), exchanges
-// through LDS either as whole complex values or split into real and
-// imaginary halves (half the LDS per tile, twice the barriers).
-//   AX = 0 (y lines, rows K apart): up to 1024 threads and 128 KiB of LDS,
-//          one wide tile per CU; measured best for short strides.
-//   AX = 1 (x lines, rows megabytes apart): up to 512 threads and 64 KiB,
-//          two tiles per CU (N <= 1024; longer lines use the AX = 0 shape).
-// TC is at most 16 columns (256 B runs in FP64) unless the lines are so
-// short that 256 threads need more.
+// Tile shape of the strided pass: TC columns of length N per workgroup, E
+// elements per thread (TPT = N/E threads per column), exchanges through LDS
+// either as whole complex values or split into real and imaginary halves
+// (half the LDS per tile, twice the barriers).  Chosen by measurement at
+// 1024^3 (FP64: y 16 columns, 512 threads, 128 KiB; x 8 columns, 256
+// threads, 64 KiB; FP32: 16 columns, 1024 threads, 64 KiB, both axes):
+//   AX = 0 (y lines, rows K apart) and any N >= 2048 get the wide budget,
+//   AX = 1 (x lines, rows megabytes apart) keeps two tiles per CU in FP64.
+// TC is at most 16 columns unless the lines are so short that 256 threads
+// need more.
 template <typename T, int N, int AX>
 struct sshape {
-    static constexpr int E = 16;
-    static constexpr int TPT = N / E;
+    static constexpr bool F64 = sizeof(T) == 8;
     static constexpr bool WIDE = AX == 0 || N >= 2048;
-    static constexpr int MAXT = WIDE ? 1024 : 512;
-    static constexpr int LDS = WIDE ? 131072 : 65536;
+    static constexpr int E = F64 ? (N >= 512 ? 32 : 16) : (N >= 2048 ? 32 : 16);
+    static constexpr int TPT = N / E;
+    static constexpr int MAXT = F64 ? (WIDE ? 512 : 256) : 1024;
+    static constexpr int LDS = (F64 ? WIDE : N >= 2048) ? 131072 : 65536;
     static constexpr int TC_T = MAXT / TPT;
     static constexpr int CAP = (256 / TPT) > 16 ? (256 / TPT) : 16;
     static constexpr int FULL = LDS / (N * int(sizeof(cx<T>)));
@@ -178,11 +189,11 @@ struct sshape {
     static constexpr bool SPLIT = TC > FULL;
 };
 
-template <typename T, int N, int TC, bool SPLIT, int S>
-__global__ __launch_bounds__(TC * N / 16) void k_strided(
+template <typename T, int N, int TC, bool SPLIT, int S, int E = 16>
+__global__ __launch_bounds__(TC * N / E) void k_strided(
     cx<T>* __restrict__ data, const cx<T>* __restrict__ tw, int64_t m_cols,
     int64_t tiles_m, line_map lm) {
-    constexpr int E = 16, TPT = N / E;
+    constexpr int TPT = N / E;
     __shared__ cx<T> lds[SPLIT ? (N * TC + 1) / 2 : N * TC];
 
     const int c = threadIdx.x % TC;
@@ -241,10 +252,11 @@ __global__ __launch_bounds__(kThreads) void k_pack(
 template <typename T, int N>
 static hipError_t z_r2c_n(const void* in, void* out, const void* tw, int64_t rows,
                           row_map map, double me, double mi, hipStream_t s) {
-    constexpr int RPB = zshape<N / 2>::RPB;
-    const int64_t blocks = (rows + RPB - 1) / RPB;
+    using C = zcfg<T, true>;
+    using Z = zshape<N / 2, C::EMAX, C::THREADS>;
+    const int64_t blocks = (rows + Z::RPB - 1) / Z::RPB;
     if (blocks == 0) return hipSuccess;
-    hipLaunchKernelGGL((k_z_r2c<T, N>), dim3(blocks), dim3(kThreads), 0, s,
+    hipLaunchKernelGGL((k_z_r2c<T, N, C::EMAX, C::THREADS>), dim3(blocks), dim3(Z::NT), 0, s,
                        static_cast<const T*>(in), static_cast<cx<T>*>(out),
                        static_cast<const cx<T>*>(tw), rows, map, T(me), T(mi));
     return hipGetLastError();
@@ -253,10 +265,11 @@ static hipError_t z_r2c_n(const void* in, void* out, const void* tw, int64_t row
 template <typename T, int N>
 static hipError_t z_c2r_n(const void* in, void* out, const void* tw, int64_t rows,
                           row_map map, double me, double mi, hipStream_t s) {
-    constexpr int RPB = zshape<N / 2>::RPB;
-    const int64_t blocks = (rows + RPB - 1) / RPB;
+    using C = zcfg<T, false>;
+    using Z = zshape<N / 2, C::EMAX, C::THREADS>;
+    const int64_t blocks = (rows + Z::RPB - 1) / Z::RPB;
     if (blocks == 0) return hipSuccess;
-    hipLaunchKernelGGL((k_z_c2r<T, N>), dim3(blocks), dim3(kThreads), 0, s,
+    hipLaunchKernelGGL((k_z_c2r<T, N, C::EMAX, C::THREADS>), dim3(blocks), dim3(Z::NT), 0, s,
                        static_cast<const cx<T>*>(in), static_cast<T*>(out),
                        static_cast<const cx<T>*>(tw), rows, map, T(me), T(mi));
     return hipGetLastError();
@@ -272,11 +285,11 @@ static hipError_t strided_ax(int sign, void* data, const void* tw, int64_t m_col
     if (blocks == 0) return hipSuccess;
     const dim3 threads(TC * SH::TPT);
     if (sign < 0)
-        hipLaunchKernelGGL((k_strided<T, N, TC, SH::SPLIT, -1>), dim3(blocks), threads, 0, s,
+        hipLaunchKernelGGL((k_strided<T, N, TC, SH::SPLIT, -1, SH::E>), dim3(blocks), threads, 0, s,
                            static_cast<cx<T>*>(data), static_cast<const cx<T>*>(tw),
                            m_cols, tiles_m, lm);
     else
-        hipLaunchKernelGGL((k_strided<T, N, TC, SH::SPLIT, +1>), dim3(blocks), threads, 0, s,
+        hipLaunchKernelGGL((k_strided<T, N, TC, SH::SPLIT, +1, SH::E>), dim3(blocks), threads, 0, s,
                            static_cast<cx<T>*>(data), static_cast<const cx<T>*>(tw),
                            m_cols, tiles_m, lm);
     return hipGetLastError();

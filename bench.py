@@ -142,9 +142,13 @@ def time_pairs(fn, steps: int, warmup: int) -> float:
 
 
 def variants(n: int, steps: int, x64: torch.Tensor, dev) -> dict:
-    """The FP32 round trip and the adjoint pair beside the FP64 line.
+    """The FP32 forms and the adjoint pair beside the FP64 line.
 
-    fp32: the same round trip on the FP32 values of the FP64 input.
+    fp32, fp32_mfma_bf16x2, fp32_mfma_bf16x3: the same round trip on the FP32
+    values of the FP64 input, with every stage on the vector ALUs or with the
+    first radix-16 stage of the y and x passes on the matrix cores (2 or 3
+    BF16 terms per operand); each forward spectrum is compared with the FP64
+    path's on the same GPU.
     adjoint_f64: the gradient pair of a loss through both transforms,
     C2R^T (scale w R2C) then R2C^T (C2R(G/w)), on the FP64 input.
     """
@@ -153,24 +157,31 @@ def variants(n: int, steps: int, x64: torch.Tensor, dev) -> dict:
     out = {}
     gflop = gflop_pair(n)
     k = n // 2 + 1
-    # FP32 round trip
-    p32 = Plan(n, torch.float32, device=dev)
+    p64 = Plan(n, torch.float64, device=dev)
+    F64 = p64.r2c(x64)
+    f64_norm = torch.linalg.vector_norm(F64).item()
     x32 = x64.float()
-    F32 = p32.empty_spectrum()
-    y32 = p32.empty_real()
-    ms = time_pairs(lambda: (p32.r2c(x32, F32), p32.c2r(F32, y32, 1.0 / n ** 3)),
-                    steps, 2)
-    err = (torch.linalg.vector_norm(y32.double() - x64)
-           / torch.linalg.vector_norm(x64)).item()
     R, C = n ** 3 * 4, n * n * k * 8
-    out["fp32"] = {"ms_per_pair": round(ms, 4), "GFLOPs": round(gflop / (ms * 1e-3), 2),
-                   "pair_hbm_roofline_frac": round(2 * (R + 5 * C) / (ms * 1e-3) / 1e9
-                                                   / PEAK_HBM_GBS, 4),
-                   "roundtrip_rel_l2_vs_fp64_input": err}
-    del x32, F32, y32, p32
+    for name, terms in (("fp32", 0), ("fp32_mfma_bf16x2", 2), ("fp32_mfma_bf16x3", 3)):
+        p32 = Plan(n, torch.float32, device=dev, mfma_terms=terms)
+        F32 = p32.r2c(x32)
+        fwd_err = (torch.linalg.vector_norm(F32.to(torch.complex128) - F64).item()
+                   / f64_norm)
+        y32 = p32.empty_real()
+        ms = time_pairs(lambda: (p32.r2c(x32, F32), p32.c2r(F32, y32, 1.0 / n ** 3)),
+                        steps, 2)
+        rt = (torch.linalg.vector_norm(y32.double() - x64)
+              / torch.linalg.vector_norm(x64)).item()
+        out[name] = {"ms_per_pair": round(ms, 4), "GFLOPs": round(gflop / (ms * 1e-3), 2),
+                     "pair_hbm_roofline_frac": round(2 * (R + 5 * C) / (ms * 1e-3) / 1e9
+                                                     / PEAK_HBM_GBS, 4),
+                     "forward_rel_l2_vs_fp64_path": fwd_err,
+                     "roundtrip_rel_l2_vs_fp64_input": rt}
+        del F32, y32, p32
+        torch.cuda.empty_cache()
+    del x32, F64
     torch.cuda.empty_cache()
     # adjoint pair in FP64
-    p64 = Plan(n, torch.float64, device=dev)
     G = p64.empty_spectrum()
     h = p64.empty_real()
     ms = time_pairs(lambda: (p64.c2r_adjoint(x64, G, 1.0 / n ** 3),

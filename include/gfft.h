@@ -56,7 +56,15 @@ enum {
      * chunk per destination rank, section 3 steps 2-3), and exec_c2r reads
      * that order.  The reorder is folded into the z pass's stores/loads, so
      * it costs no extra pass. */
-    GFFT_FUSE_PACK = 1u << 0
+    GFFT_FUSE_PACK = 1u << 0,
+    /* FP32 plans, N >= 32: run the first radix-16 stage of the y and x passes
+     * on the matrix cores as a real 32x32 GEMM (v_mfma_f32_32x32x16_bf16)
+     * with every FP32 operand split into 2 (or 3) BF16 terms and FP32
+     * accumulation.  A precision/speed variant of the FP32 vector path:
+     * relative error per product about 2^-16 (2 terms) or 2^-24 (3 terms).
+     * At most one of the two; GFFT_E_UNSUPPORTED for FP64 or N < 32. */
+    GFFT_MFMA_BF16X2 = 1u << 1,
+    GFFT_MFMA_BF16X3 = 1u << 2
 };
 
 typedef struct gfft_plan gfft_plan;
@@ -83,7 +91,8 @@ typedef struct {
  *            one GPU (p = 1); X < n is rank r's slab of p = n/X ranks
  *            (section 2, slab decomposition).
  *   batch  : >= 1 independent grids per exec call.
- *   flags  : bitwise OR of GFFT_FUSE_PACK (or 0).
+ *   flags  : bitwise OR of GFFT_FUSE_PACK and at most one of
+ *            GFFT_MFMA_BF16X2 / GFFT_MFMA_BF16X3 (or 0).
  * On success *out receives the plan.  The plan owns small device tables
  * (FP64-derived twiddle factors rounded once to the working precision) on
  * the device that is current at creation; exec calls must run with that

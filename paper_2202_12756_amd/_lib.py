@@ -24,6 +24,8 @@ GFFT_F64 = 0
 GFFT_F32 = 1
 
 GFFT_FUSE_PACK = 1 << 0
+GFFT_MFMA_BF16X2 = 1 << 1
+GFFT_MFMA_BF16X3 = 1 << 2
 
 # Every symbol include/gfft.h declares.
 EXPORTS = (

@@ -22,7 +22,7 @@ struct gfft_plan {
 
 namespace {
 
-constexpr uint32_t kKnownFlags = GFFT_FUSE_PACK;
+constexpr uint32_t kKnownFlags = GFFT_FUSE_PACK | GFFT_MFMA_BF16X2 | GFFT_MFMA_BF16X3;
 
 int ilog2(int64_t v) {
     int l = 0;
@@ -130,14 +130,20 @@ gfft_status run_z_c2r(const gfft_plan* p, const void* in, void* out, double scal
                                          p->batch * p->x * p->n, zmap(p), me, mi, s));
 }
 
+int mfma_terms(const gfft_plan* p) {
+    if (p->flags & GFFT_MFMA_BF16X3) return 3;
+    if (p->flags & GFFT_MFMA_BF16X2) return 2;
+    return 0;
+}
+
 gfft_status run_y(const gfft_plan* p, void* data, int sign, hipStream_t s) {
-    return hip_status(gfft::launch_strided(f64(p), int(p->n), 0, sign, data, p->tw, p->k,
-                                           p->batch * p->x, ymap(p), s));
+    return hip_status(gfft::launch_strided(f64(p), int(p->n), 0, mfma_terms(p), sign, data,
+                                           p->tw, p->k, p->batch * p->x, ymap(p), s));
 }
 
 gfft_status run_x(const gfft_plan* p, void* data, int sign, hipStream_t s) {
-    return hip_status(gfft::launch_strided(f64(p), int(p->n), 1, sign, data, p->tw,
-                                           p->y * p->k, p->batch, xmap(p), s));
+    return hip_status(gfft::launch_strided(f64(p), int(p->n), 1, mfma_terms(p), sign, data,
+                                           p->tw, p->y * p->k, p->batch, xmap(p), s));
 }
 
 gfft_status check_r2c_args(const gfft_plan* p, const void* in, const void* out) {
@@ -200,6 +206,9 @@ gfft_status gfft_plan_create(gfft_plan** out, int64_t n, gfft_dtype dtype, int64
     if (batch < 1 || slab_x < 1 || n < 1) return GFFT_E_INVALID_ARG;
     if (!pow2(n) || n < 16 || n > 4096) return GFFT_E_UNSUPPORTED;
     if (slab_x > n || n % slab_x != 0) return GFFT_E_INVALID_ARG;
+    const uint32_t mf = flags & (GFFT_MFMA_BF16X2 | GFFT_MFMA_BF16X3);
+    if (mf == (GFFT_MFMA_BF16X2 | GFFT_MFMA_BF16X3)) return GFFT_E_INVALID_ARG;
+    if (mf && (dtype != GFFT_F32 || n < 32)) return GFFT_E_UNSUPPORTED;
     // sizes must stay addressable with 64-bit element offsets
     const int64_t k = n / 2 + 1;
     if (batch > (int64_t(1) << 62) / (slab_x * n * k * 2 * 8)) return GFFT_E_UNSUPPORTED;

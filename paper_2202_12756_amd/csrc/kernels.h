@@ -33,9 +33,12 @@ hipError_t launch_z_c2r(bool f64, int n, const void* in, void* out, const void* 
                         int64_t rows, row_map map, double mul_edge, double mul_int,
                         hipStream_t s);
 // axis 0: y lines (short stride); axis 1: x lines (long stride).  Picks the
-// tile shape measured best for that stride.
-hipError_t launch_strided(bool f64, int n, int axis, int sign, void* data, const void* tw,
-                          int64_t m_cols, int64_t n_b, line_map lm, hipStream_t s);
+// tile shape measured best for that stride.  mfma_terms 2 or 3 (FP32, N >= 32
+// only) runs the first radix-16 stage on the matrix cores with that many
+// BF16 terms per operand; 0 keeps every stage on the vector ALUs.
+hipError_t launch_strided(bool f64, int n, int axis, int mfma_terms, int sign, void* data,
+                          const void* tw, int64_t m_cols, int64_t n_b, line_map lm,
+                          hipStream_t s);
 // Copy `chunks` runs of `len` complex values: run c = (bb, j, xl) goes from
 // natural offset bb*X*N*K + (xl*N + j*Y)*K to send offset
 // bb*X*N*K + (j*X + xl)*Y*K (to_send = true) or back (to_send = false).

@@ -15,6 +15,7 @@
 #include "cx.h"
 #include "engine.h"
 #include "kernels.h"
+#include "mfma_dft16.h"
 
 namespace gfft {
 
@@ -172,11 +173,11 @@ __global__ __launch_bounds__((zshape<N / 2, EMAX, THREADS>::NT)) void k_z_c2r(
 //   AX = 1 (x lines, rows megabytes apart) keeps two tiles per CU in FP64.
 // TC is at most 16 columns unless the lines are so short that 256 threads
 // need more.
-template <typename T, int N, int AX>
+template <typename T, int N, int AX, bool MFMA = false>
 struct sshape {
     static constexpr bool F64 = sizeof(T) == 8;
     static constexpr bool WIDE = AX == 0 || N >= 2048;
-    static constexpr int E = F64 ? (N >= 512 ? 32 : 16) : (N >= 2048 ? 32 : 16);
+    static constexpr int E = MFMA ? 16 : F64 ? (N >= 512 ? 32 : 16) : (N >= 2048 ? 32 : 16);
     static constexpr int TPT = N / E;
     static constexpr int MAXT = F64 ? (WIDE ? 512 : 256) : 1024;
     static constexpr int LDS = (F64 ? WIDE : N >= 2048) ? 131072 : 65536;
@@ -189,7 +190,7 @@ struct sshape {
     static constexpr bool SPLIT = TC > FULL;
 };
 
-template <typename T, int N, int TC, bool SPLIT, int S, int E = 16>
+template <typename T, int N, int TC, bool SPLIT, int S, int E = 16, int MF = 0>
 __global__ __launch_bounds__(TC * N / E) void k_strided(
     cx<T>* __restrict__ data, const cx<T>* __restrict__ tw, int64_t m_cols,
     int64_t tiles_m, line_map lm) {
@@ -200,29 +201,92 @@ __global__ __launch_bounds__(TC * N / E) void k_strided(
     const int t = threadIdx.x / TC;
     const int64_t tile = xcd_tile(blockIdx.x, gridDim.x);
     const int64_t b = tile / tiles_m;
-    const int64_t m = (tile - b * tiles_m) * TC + c;
+    const int64_t m0 = (tile - b * tiles_m) * TC;
+    const int64_t m = m0 + c;
     const bool valid = m < m_cols;
     const int64_t ymask = (int64_t(1) << lm.lg_y) - 1;
-    cx<T>* base = data + (b >> lm.lg_bx) * lm.b_hi +
-                  (b & ((int64_t(1) << lm.lg_bx) - 1)) * lm.b_lo + m;
+    cx<T>* plane = data + (b >> lm.lg_bx) * lm.b_hi + (b & ((int64_t(1) << lm.lg_bx) - 1)) * lm.b_lo;
+    cx<T>* base = plane + m;
+    auto off = [&](int64_t n) { return (n >> lm.lg_y) * lm.s_hi + (n & ymask) * lm.s_lo; };
 
     cx<T> a[E];
+    if constexpr (MF == 0) {
 #pragma unroll
-    for (int i = 0; i < E; ++i) {
-        const int64_t n = t + i * TPT;
-        a[i] = valid ? base[(n >> lm.lg_y) * lm.s_hi + (n & ymask) * lm.s_lo]
-                     : cx<T>{T(0), T(0)};
+        for (int i = 0; i < E; ++i) {
+            const int64_t n = t + i * TPT;
+            a[i] = valid ? base[off(n)] : cx<T>{T(0), T(0)};
+        }
+        if constexpr (SPLIT)
+            fft_regs<T, N, E, S>(a, t, tw, 1,
+                                 xch_split<T, idx_cols<TC>>{reinterpret_cast<T*>(lds), {c}});
+        else
+            fft_regs<T, N, E, S>(a, t, tw, 1, xch_full<T, idx_cols<TC>>{lds, {c}});
+    } else {
+        // First radix-16 stage on the matrix cores.  The wave's 64 butterflies
+        // (those of its own threads, j = t for thread (c, t)) go in two groups
+        // of 32; lane (h, n) loads inputs 8h..8h+7 of butterfly 32g + n.
+        static_assert(sizeof(T) == 4 && E == 16 && N >= 32, "MFMA stage: FP32, radix-16 first stage");
+        const int lane = threadIdx.x & 63, h = lane >> 5;
+        const int wbase = threadIdx.x & ~63;
+        dft16_mfma<S, MF> dft;
+        dft.init(lane);
+        cx<float> y[2][8];
+        int bc[2], bt[2];
+#pragma unroll
+        for (int g = 0; g < 2; ++g) {
+            const int tid_b = wbase + 32 * g + (lane & 31);
+            bc[g] = tid_b % TC;
+            bt[g] = tid_b / TC;
+            const bool vb = m0 + bc[g] < m_cols;
+            cx<float> in[8];
+#pragma unroll
+            for (int j = 0; j < 8; ++j) {
+                const int64_t n = bt[g] + (8 * h + j) * TPT;
+                in[j] = vb ? plane[m0 + bc[g] + off(n)] : cx<float>{0.f, 0.f};
+            }
+            dft.run(in, y[g]);
+        }
+        // exchange: output r of butterfly (c_b, t_b) goes to position 16 t_b + r
+        const idx_cols<TC> pos_c{c};
+        if constexpr (SPLIT) {
+            T* buf = reinterpret_cast<T*>(lds);
+#pragma unroll
+            for (int part = 0; part < 2; ++part) {
+#pragma unroll
+                for (int g = 0; g < 2; ++g)
+#pragma unroll
+                    for (int v = 0; v < 8; ++v)
+                        buf[(16 * bt[g] + dft16_out_index(h, v)) * TC + bc[g]] = part ? y[g][v].y : y[g][v].x;
+                __syncthreads();
+#pragma unroll
+                for (int i = 0; i < E; ++i) {
+                    const T val = buf[pos_c(t + i * TPT)];
+                    if (part) a[i].y = val; else a[i].x = val;
+                }
+                __syncthreads();
+            }
+        } else {
+#pragma unroll
+            for (int g = 0; g < 2; ++g)
+#pragma unroll
+                for (int v = 0; v < 8; ++v)
+                    lds[(16 * bt[g] + dft16_out_index(h, v)) * TC + bc[g]] = y[g][v];
+            __syncthreads();
+#pragma unroll
+            for (int i = 0; i < E; ++i) a[i] = lds[pos_c(t + i * TPT)];
+            __syncthreads();
+        }
+        if constexpr (SPLIT)
+            fft_from<T, N, E, S, 16>(a, t, tw, 1,
+                                     xch_split<T, idx_cols<TC>>{reinterpret_cast<T*>(lds), {c}});
+        else
+            fft_from<T, N, E, S, 16>(a, t, tw, 1, xch_full<T, idx_cols<TC>>{lds, {c}});
     }
-    if constexpr (SPLIT)
-        fft_regs<T, N, E, S>(a, t, tw, 1,
-                             xch_split<T, idx_cols<TC>>{reinterpret_cast<T*>(lds), {c}});
-    else
-        fft_regs<T, N, E, S>(a, t, tw, 1, xch_full<T, idx_cols<TC>>{lds, {c}});
     if (!valid) return;
 #pragma unroll
     for (int i = 0; i < E; ++i) {
         const int64_t n = t + i * TPT;
-        base[(n >> lm.lg_y) * lm.s_hi + (n & ymask) * lm.s_lo] = a[i];
+        base[off(n)] = a[i];
     }
 }
 
@@ -275,31 +339,40 @@ static hipError_t z_c2r_n(const void* in, void* out, const void* tw, int64_t row
     return hipGetLastError();
 }
 
-template <typename T, int N, int AX>
+template <typename T, int N, int AX, int MF>
 static hipError_t strided_ax(int sign, void* data, const void* tw, int64_t m_cols,
                              int64_t n_b, line_map lm, hipStream_t s) {
-    using SH = sshape<T, N, AX>;
+    using SH = sshape<T, N, AX, MF != 0>;
     constexpr int TC = SH::TC;
     const int64_t tiles_m = (m_cols + TC - 1) / TC;
     const int64_t blocks = tiles_m * n_b;
     if (blocks == 0) return hipSuccess;
     const dim3 threads(TC * SH::TPT);
     if (sign < 0)
-        hipLaunchKernelGGL((k_strided<T, N, TC, SH::SPLIT, -1, SH::E>), dim3(blocks), threads, 0, s,
-                           static_cast<cx<T>*>(data), static_cast<const cx<T>*>(tw),
+        hipLaunchKernelGGL((k_strided<T, N, TC, SH::SPLIT, -1, SH::E, MF>), dim3(blocks), threads,
+                           0, s, static_cast<cx<T>*>(data), static_cast<const cx<T>*>(tw),
                            m_cols, tiles_m, lm);
     else
-        hipLaunchKernelGGL((k_strided<T, N, TC, SH::SPLIT, +1, SH::E>), dim3(blocks), threads, 0, s,
-                           static_cast<cx<T>*>(data), static_cast<const cx<T>*>(tw),
+        hipLaunchKernelGGL((k_strided<T, N, TC, SH::SPLIT, +1, SH::E, MF>), dim3(blocks), threads,
+                           0, s, static_cast<cx<T>*>(data), static_cast<const cx<T>*>(tw),
                            m_cols, tiles_m, lm);
     return hipGetLastError();
 }
 
 template <typename T, int N>
-static hipError_t strided_n(int axis, int sign, void* data, const void* tw, int64_t m_cols,
-                            int64_t n_b, line_map lm, hipStream_t s) {
-    if (axis == 0) return strided_ax<T, N, 0>(sign, data, tw, m_cols, n_b, lm, s);
-    return strided_ax<T, N, 1>(sign, data, tw, m_cols, n_b, lm, s);
+static hipError_t strided_n(int axis, int mfma_terms, int sign, void* data, const void* tw,
+                            int64_t m_cols, int64_t n_b, line_map lm, hipStream_t s) {
+    if constexpr (sizeof(T) == 4 && N >= 32) {
+        if (mfma_terms == 2)
+            return axis == 0 ? strided_ax<T, N, 0, 2>(sign, data, tw, m_cols, n_b, lm, s)
+                             : strided_ax<T, N, 1, 2>(sign, data, tw, m_cols, n_b, lm, s);
+        if (mfma_terms == 3)
+            return axis == 0 ? strided_ax<T, N, 0, 3>(sign, data, tw, m_cols, n_b, lm, s)
+                             : strided_ax<T, N, 1, 3>(sign, data, tw, m_cols, n_b, lm, s);
+    }
+    if (mfma_terms != 0) return hipErrorInvalidValue;
+    if (axis == 0) return strided_ax<T, N, 0, 0>(sign, data, tw, m_cols, n_b, lm, s);
+    return strided_ax<T, N, 1, 0>(sign, data, tw, m_cols, n_b, lm, s);
 }
 
 #define GFFT_DISPATCH_N(FN, T, ...)                 \
@@ -328,10 +401,11 @@ hipError_t launch_z_c2r(bool f64, int n, const void* in, void* out, const void* 
     GFFT_DISPATCH_N(z_c2r_n, float, in, out, tw, rows, map, me, mi, s)
 }
 
-hipError_t launch_strided(bool f64, int n, int axis, int sign, void* data, const void* tw,
-                          int64_t m_cols, int64_t n_b, line_map lm, hipStream_t s) {
-    if (f64) { GFFT_DISPATCH_N(strided_n, double, axis, sign, data, tw, m_cols, n_b, lm, s) }
-    GFFT_DISPATCH_N(strided_n, float, axis, sign, data, tw, m_cols, n_b, lm, s)
+hipError_t launch_strided(bool f64, int n, int axis, int mfma_terms, int sign, void* data,
+                          const void* tw, int64_t m_cols, int64_t n_b, line_map lm,
+                          hipStream_t s) {
+    if (f64) { GFFT_DISPATCH_N(strided_n, double, axis, mfma_terms, sign, data, tw, m_cols, n_b, lm, s) }
+    GFFT_DISPATCH_N(strided_n, float, axis, mfma_terms, sign, data, tw, m_cols, n_b, lm, s)
 }
 
 hipError_t launch_pack(bool f64, const void* src, void* dst, int64_t chunks, int lg_x,

@@ -24,11 +24,14 @@ class Plan:
     Layouts (C order, z fastest): real [batch, X, N, N]; half spectrum
     [batch, X, N, K] complex, or the send order [batch, p, X, N/p, K] when
     ``fuse_pack``; x-pencil [batch, N, N/p, K].  For batch == 1 the leading
-    batch dimension may be omitted.
+    batch dimension may be omitted.  ``mfma_terms`` (FP32 only) runs the first
+    radix-16 stage of the y and x passes on the matrix cores with 2 or 3
+    BF16 terms per operand.
     """
 
     def __init__(self, n: int, dtype=torch.float64, slab_x: int | None = None,
-                 batch: int = 1, fuse_pack: bool = False, device=None):
+                 batch: int = 1, fuse_pack: bool = False, device=None,
+                 mfma_terms: int = 0):
         if dtype not in _REAL:
             raise TypeError("dtype must be torch.float64 or torch.float32")
         self.n = int(n)
@@ -38,7 +41,14 @@ class Plan:
         self.batch = int(batch)
         self.fuse_pack = bool(fuse_pack)
         self.device = torch.device(device if device is not None else "cuda")
+        self.mfma_terms = int(mfma_terms)
         flags = _lib.GFFT_FUSE_PACK if fuse_pack else 0
+        if self.mfma_terms not in (0, 2, 3):
+            raise ValueError("mfma_terms must be 0, 2 or 3")
+        if self.mfma_terms == 2:
+            flags |= _lib.GFFT_MFMA_BF16X2
+        elif self.mfma_terms == 3:
+            flags |= _lib.GFFT_MFMA_BF16X3
         with torch.cuda.device(self.device):
             st, h = _lib.gfft_plan_create(self.n, _REAL[dtype], self.slab_x,
                                           self.batch, flags)

@@ -51,6 +51,11 @@ def test_status_strings_and_version():
     ((64, 0, 64, 1, 1 << 7), _lib.GFFT_E_INVALID_ARG),         # unknown flag
     ((0, 0, 1, 1, 0), _lib.GFFT_E_INVALID_ARG),                # N = 0
     ((4096, 0, 4096, 1 << 40, 0), _lib.GFFT_E_UNSUPPORTED),    # size overflow
+    ((64, 1, 64, 1, 2), None),                                 # FP32 + 2-term MFMA
+    ((64, 1, 64, 1, 4), None),                                 # FP32 + 3-term MFMA
+    ((64, 0, 64, 1, 2), _lib.GFFT_E_UNSUPPORTED),              # MFMA needs FP32
+    ((16, 1, 16, 1, 4), _lib.GFFT_E_UNSUPPORTED),              # MFMA needs N >= 32
+    ((64, 1, 64, 1, 6), _lib.GFFT_E_INVALID_ARG),              # both MFMA flags
 ])
 def test_plan_create_validates_on_host(args, expect):
     st, h = _lib.gfft_plan_create(*args)

@@ -122,3 +122,44 @@ def test_paper_field_round_trip(n):
             for sy in (1, -1):
                 ref[(sx * a) % n, (sy * b) % n, c] = 1j * sx * sy
     assert np.max(np.abs(Fh - ref)) <= 1e-15 * n
+
+
+@pytest.mark.parametrize("terms,bound", [(2, 1e-4), (3, 5e-6)])
+@pytest.mark.parametrize("n", [32, 64, 256, 1024])
+@pytest.mark.parametrize("sign", [-1, 1])
+def test_mfma_split_bf16_strided(n, terms, bound, sign):
+    """First radix-16 stage on the matrix cores: error against the FP64
+    oracle (2 BF16 terms: about 2^-16 per product; 3 terms: FP32 level)."""
+    x = planes_for(n)
+    p = Plan(n, torch.float32, slab_x=x if x < n else None, mfma_terms=terms)
+    g, gref = cplx_input(p.spectrum_shape, 8000 + n, torch.float32)
+    p.y_c2c(g, sign)
+    torch.cuda.synchronize()
+    err = rel_l2(host(g), oracle.c2c_axis(gref, -2, sign))
+    print(f"mfma bf16x{terms} y pass n={n} sign={sign}: rel-L2 {err:.3e}")
+    assert err <= bound
+    y = max(1, min(n, 2 ** 21 // (n * (n // 2 + 1))))
+    y = 1 << (y.bit_length() - 1)
+    q = Plan(n, torch.float32, slab_x=y, mfma_terms=terms)
+    pen, pref = cplx_input(q.pencil_shape, 8100 + n, torch.float32)
+    q.x_c2c(pen, sign)
+    torch.cuda.synchronize()
+    err = rel_l2(host(pen), oracle.c2c_axis(pref, -3, sign))
+    print(f"mfma bf16x{terms} x pass n={n} sign={sign}: rel-L2 {err:.3e}")
+    assert err <= bound
+
+
+@pytest.mark.parametrize("terms", [2, 3])
+def test_mfma_full_round_trip(terms):
+    n = 64
+    p = Plan(n, torch.float32, mfma_terms=terms)
+    xin, xref = real_input(p.real_shape, 8200, torch.float32)
+    F = p.r2c(xin)
+    torch.cuda.synchronize()
+    err = rel_l2(host(F), oracle.r2c3d(xref))
+    back = p.c2r(F, scale=1.0 / n ** 3)
+    torch.cuda.synchronize()
+    rt = rel_l2(host(back), xref)
+    print(f"mfma bf16x{terms} 64^3: forward rel-L2 {err:.3e}, round trip {rt:.3e}")
+    assert err <= (1e-4 if terms == 2 else 5e-6)
+    assert rt <= (1e-4 if terms == 2 else 5e-6)

@@ -187,15 +187,20 @@ struct sshape {
     static constexpr int A0 = TC_T < CAP ? TC_T : CAP;
     static constexpr int A1 = A0 < 2 * FULL ? A0 : 2 * FULL;
     static constexpr int TC = A1 < 1 ? 1 : A1;
-    static constexpr bool SPLIT = TC > FULL;
+    static constexpr int XP = TC > FULL ? 2 : 1;
 };
 
-template <typename T, int N, int TC, bool SPLIT, int S, int E = 16, int MF = 0>
+// XP: LDS rounds per exchange.  1 = whole complex values, 2 = real then
+// imaginary parts, 2P (P > 1) = real and imaginary parts of P position
+// ranges; the LDS tile is N*TC/XP complex values.
+template <typename T, int N, int TC, int XP, int S, int E = 16, int MF = 0>
 __global__ __launch_bounds__(TC * N / E) void k_strided(
     cx<T>* __restrict__ data, const cx<T>* __restrict__ tw, int64_t m_cols,
     int64_t tiles_m, line_map lm) {
     constexpr int TPT = N / E;
-    __shared__ cx<T> lds[SPLIT ? (N * TC + 1) / 2 : N * TC];
+    constexpr bool SPLIT = XP == 2;
+    static_assert(XP == 1 || XP % 2 == 0, "XP must be 1 or even");
+    __shared__ cx<T> lds[(N * TC + XP - 1) / XP];
 
     const int c = threadIdx.x % TC;
     const int t = threadIdx.x / TC;
@@ -216,12 +221,16 @@ __global__ __launch_bounds__(TC * N / E) void k_strided(
             const int64_t n = t + i * TPT;
             a[i] = valid ? base[off(n)] : cx<T>{T(0), T(0)};
         }
-        if constexpr (SPLIT)
+        if constexpr (XP > 2)
+            fft_regs<T, N, E, S>(a, t, tw, 1,
+                                 xch_parts<T, idx_cols<TC>, XP / 2>{reinterpret_cast<T*>(lds), {c}});
+        else if constexpr (SPLIT)
             fft_regs<T, N, E, S>(a, t, tw, 1,
                                  xch_split<T, idx_cols<TC>>{reinterpret_cast<T*>(lds), {c}});
         else
             fft_regs<T, N, E, S>(a, t, tw, 1, xch_full<T, idx_cols<TC>>{lds, {c}});
     } else {
+        static_assert(XP <= 2, "MFMA stage: whole or re/im exchange");
         // First radix-16 stage on the matrix cores.  The wave's 64 butterflies
         // (those of its own threads, j = t for thread (c, t)) go in two groups
         // of 32; lane (h, n) loads inputs 8h..8h+7 of butterfly 32g + n.
@@ -349,11 +358,11 @@ static hipError_t strided_ax(int sign, void* data, const void* tw, int64_t m_col
     if (blocks == 0) return hipSuccess;
     const dim3 threads(TC * SH::TPT);
     if (sign < 0)
-        hipLaunchKernelGGL((k_strided<T, N, TC, SH::SPLIT, -1, SH::E, MF>), dim3(blocks), threads,
+        hipLaunchKernelGGL((k_strided<T, N, TC, SH::XP, -1, SH::E, MF>), dim3(blocks), threads,
                            0, s, static_cast<cx<T>*>(data), static_cast<const cx<T>*>(tw),
                            m_cols, tiles_m, lm);
     else
-        hipLaunchKernelGGL((k_strided<T, N, TC, SH::SPLIT, +1, SH::E, MF>), dim3(blocks), threads,
+        hipLaunchKernelGGL((k_strided<T, N, TC, SH::XP, +1, SH::E, MF>), dim3(blocks), threads,
                            0, s, static_cast<cx<T>*>(data), static_cast<const cx<T>*>(tw),
                            m_cols, tiles_m, lm);
     return hipGetLastError();

@@ -31,20 +31,50 @@ struct stage_radix {
 };
 
 // Where element `pos` of this thread's transform lives in an LDS buffer.
-//   columns: TC transforms side by side, element (pos, c) at pos*TC + c
-//   rows:    one transform per row, element pos at off + pos
-template <int TC>
-struct idx_cols {
-    int c;
-    __device__ __forceinline__ int operator()(int pos) const { return pos * TC + c; }
+// The first exchange sends consecutive threads' outputs R0 positions apart
+// (R0 = 2^PS, the first radix), which would put them in the same LDS banks;
+// one padding position after every R0 positions staggers them:
+// pad(pos) = pos + (pos >> PS).
+//   columns: TC transforms side by side, element (pos, c) at pad(pos)*TC + c
+//   rows:    one transform per row, element pos at off + pad(pos)
+template <int PS>
+__device__ __forceinline__ int lds_pad(int pos) {
+    if constexpr (PS > 0) return pos + (pos >> PS);
+    else return pos;
+}
+// Positions a transform of length N occupies once padded.
+template <int N, int PS>
+struct padded_len {
+    static constexpr int value = PS > 0 ? N + (N >> PS) : N;
 };
+template <int TC, int PS = 0>
+struct idx_cols {
+    static constexpr int SHIFT = PS;
+    int c;
+    __device__ __forceinline__ int at(int padded) const { return padded * TC + c; }
+    __device__ __forceinline__ int operator()(int pos) const { return at(lds_pad<PS>(pos)); }
+};
+template <int PS = 0>
 struct idx_rows {
+    static constexpr int SHIFT = PS;
     int off;
-    __device__ __forceinline__ int operator()(int pos) const { return off + pos; }
+    __device__ __forceinline__ int at(int padded) const { return off + padded; }
+    __device__ __forceinline__ int operator()(int pos) const { return at(lds_pad<PS>(pos)); }
+};
+// log2 of the first radix for E elements per thread
+template <int E>
+struct first_radix_shift {
+    static constexpr int R0 = E < 16 ? E : 16;
+    static constexpr int value = R0 >= 16 ? 4 : R0 >= 8 ? 3 : R0 >= 4 ? 2 : R0 >= 2 ? 1 : 0;
 };
 
 // Exchange after a stage: every output slot q + r*NB goes to position
 // (j - k) R + k + r L; then slot m is reloaded from position t + m*TPT.
+// Padded positions are formed so that they stay affine in r and m (a base
+// per butterfly plus compile-time steps): with R0 = 2^PS, the first stage
+// (L = 1, R = R0) writes j (R0 + 1) + r, later stages (L a multiple of R0)
+// write pad((j-k)R + k) + r (L + L/R0), and reads are
+// pad(t) + m (TPT + TPT/R0) when R0 divides TPT.
 template <int N, int E, int L, int R>
 struct xgeom {
     static constexpr int NB = E / R, TPT = N / E;
@@ -52,6 +82,30 @@ struct xgeom {
         const int q = s % NB, r = s / NB;
         const int j = t + q * TPT, k = j & (L - 1);
         return (j - k) * R + k + r * L;
+    }
+    // padded position of output slot s
+    template <int PS>
+    __device__ __forceinline__ static int out_pad(int t, int s) {
+        const int q = s % NB, r = s / NB;
+        const int j = t + q * TPT;
+        if constexpr (PS == 0) {
+            const int k = j & (L - 1);
+            return (j - k) * R + k + r * L;
+        } else if constexpr (L == 1 && R == (1 << PS)) {
+            return j * (R + 1) + r;
+        } else if constexpr (L % (1 << PS) == 0) {
+            const int k = j & (L - 1);
+            return lds_pad<PS>((j - k) * R + k) + r * (L + (L >> PS));
+        } else {
+            return lds_pad<PS>(out_pos(t, s));
+        }
+    }
+    // padded position of input slot m
+    template <int PS>
+    __device__ __forceinline__ static int in_pad(int t, int m) {
+        if constexpr (PS == 0) return t + m * TPT;
+        else if constexpr (TPT % (1 << PS) == 0) return lds_pad<PS>(t) + m * (TPT + (TPT >> PS));
+        else return lds_pad<PS>(t + m * TPT);
     }
 };
 
@@ -63,11 +117,12 @@ struct xch_full {
     template <int N, int E, int L, int R>
     __device__ __forceinline__ void run(cx<T> (&a)[E], int t) const {
         using G = xgeom<N, E, L, R>;
+        constexpr int PS = Idx::SHIFT;
 #pragma unroll
-        for (int s = 0; s < E; ++s) buf[idx(G::out_pos(t, s))] = a[s];
+        for (int s = 0; s < E; ++s) buf[idx.at(G::template out_pad<PS>(t, s))] = a[s];
         __syncthreads();
 #pragma unroll
-        for (int m = 0; m < E; ++m) a[m] = buf[idx(t + m * G::TPT)];
+        for (int m = 0; m < E; ++m) a[m] = buf[idx.at(G::template in_pad<PS>(t, m))];
         __syncthreads();
     }
 };
@@ -80,17 +135,18 @@ struct xch_split {
     template <int N, int E, int L, int R>
     __device__ __forceinline__ void run(cx<T> (&a)[E], int t) const {
         using G = xgeom<N, E, L, R>;
+        constexpr int PS = Idx::SHIFT;
 #pragma unroll
-        for (int s = 0; s < E; ++s) buf[idx(G::out_pos(t, s))] = a[s].x;
+        for (int s = 0; s < E; ++s) buf[idx.at(G::template out_pad<PS>(t, s))] = a[s].x;
         __syncthreads();
 #pragma unroll
-        for (int m = 0; m < E; ++m) a[m].x = buf[idx(t + m * G::TPT)];
+        for (int m = 0; m < E; ++m) a[m].x = buf[idx.at(G::template in_pad<PS>(t, m))];
         __syncthreads();
 #pragma unroll
-        for (int s = 0; s < E; ++s) buf[idx(G::out_pos(t, s))] = a[s].y;
+        for (int s = 0; s < E; ++s) buf[idx.at(G::template out_pad<PS>(t, s))] = a[s].y;
         __syncthreads();
 #pragma unroll
-        for (int m = 0; m < E; ++m) a[m].y = buf[idx(t + m * G::TPT)];
+        for (int m = 0; m < E; ++m) a[m].y = buf[idx.at(G::template in_pad<PS>(t, m))];
         __syncthreads();
     }
 };
@@ -100,6 +156,7 @@ struct xch_split {
 // buffer of N/PARTS reals per transform (1/(2 PARTS) of the whole-value
 // buffer).  Writes are predicated on the destination range; the reads of
 // round p are slots m in [p E/PARTS, (p+1) E/PARTS), which lie in that range.
+// (Unpadded layouts only.)
 template <typename T, class Idx, int PARTS>
 struct xch_parts {
     T* buf;
@@ -109,6 +166,7 @@ struct xch_parts {
         using G = xgeom<N, E, L, R>;
         constexpr int SEG = N / PARTS, EP = E / PARTS;
         static_assert(N % PARTS == 0 && E % PARTS == 0, "bad partition");
+        static_assert(Idx::SHIFT == 0, "partitioned exchange uses unpadded layouts");
 #pragma unroll
         for (int p = 0; p < PARTS; ++p) {
 #pragma unroll

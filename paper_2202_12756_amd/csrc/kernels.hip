@@ -49,12 +49,13 @@ struct zshape {
     static constexpr int RPB = NT / TPT;           // rows per workgroup
 };
 
-// Workgroup shape of the z passes, chosen by measurement at 1024^3:
-// FP64 R2C 8 elements per thread in 256-thread workgroups, FP64 C2R 16 per
-// thread in 64-thread workgroups, FP32 32 per thread in 64-thread ones.
-template <typename T, bool FWD>
+// Workgroup shape of the z passes, chosen by measurement at 1024^3 and
+// 4096^2 rows: FP64 R2C 8 elements per thread (16 for N >= 2048) in
+// 256-thread workgroups, FP64 C2R 16 per thread in 64-thread workgroups,
+// FP32 32 per thread in 64-thread ones.
+template <typename T, bool FWD, int N>
 struct zcfg {
-    static constexpr int EMAX = sizeof(T) == 8 ? (FWD ? 8 : 16) : 32;
+    static constexpr int EMAX = sizeof(T) == 8 ? (FWD ? (N >= 2048 ? 16 : 8) : 16) : 32;
     static constexpr int THREADS = sizeof(T) == 8 && FWD ? 256 : 64;
 };
 
@@ -66,7 +67,8 @@ __global__ __launch_bounds__((zshape<N / 2, EMAX, THREADS>::NT)) void k_z_r2c(
     constexpr int M = N / 2, K = M + 1;
     using Z = zshape<M, EMAX, THREADS>;
     constexpr int E = Z::E, TPT = Z::TPT, RPB = Z::RPB;
-    __shared__ cx<T> lds[RPB * M];
+    constexpr int PS = first_radix_shift<E>::value, MP = padded_len<M, PS>::value;
+    __shared__ cx<T> lds[RPB * MP];
 
     const int rl = threadIdx.x / TPT;
     const int t = threadIdx.x % TPT;
@@ -78,14 +80,14 @@ __global__ __launch_bounds__((zshape<N / 2, EMAX, THREADS>::NT)) void k_z_r2c(
 #pragma unroll
     for (int m = 0; m < E; ++m) a[m] = valid ? src[t + m * TPT] : cx<T>{T(0), T(0)};
 
-    cx<T>* L = lds + rl * M;
-    fft_regs<T, M, E, -1>(a, t, tw, 2, xch_full<T, idx_rows>{lds, idx_rows{rl * M}});
+    const idx_rows<PS> ix{rl * MP};
+    fft_regs<T, M, E, -1>(a, t, tw, 2, xch_full<T, idx_rows<PS>>{lds, ix});
 
     // Split Z = FFT_M(z) into the real transform:
     //   X[k] = (Z[k] + conj Z[M-k])/2 - (i/2) W_N^k (Z[k] - conj Z[M-k]),
     //   X[M] = Re Z[0] - Im Z[0].
 #pragma unroll
-    for (int m = 0; m < E; ++m) L[t + m * TPT] = a[m];
+    for (int m = 0; m < E; ++m) lds[ix.at(xgeom<M, E, 1, 1>::template in_pad<PS>(t, m))] = a[m];
     __syncthreads();
     if (!valid) return;
     cx<T>* dst = out + map_row(row, map) * K;
@@ -93,7 +95,7 @@ __global__ __launch_bounds__((zshape<N / 2, EMAX, THREADS>::NT)) void k_z_r2c(
     for (int m = 0; m < E; ++m) {
         const int k = t + m * TPT;
         const cx<T> zk = a[m];
-        const cx<T> zc = conjg(L[(M - k) & (M - 1)]);
+        const cx<T> zc = conjg(lds[ix((M - k) & (M - 1))]);
         const cx<T> A = scal(zk + zc, T(0.5));
         const cx<T> B = scal(zk - zc, T(0.5));
         const cx<T> wb = cmul(tw[k], B);
@@ -111,13 +113,14 @@ __global__ __launch_bounds__((zshape<N / 2, EMAX, THREADS>::NT)) void k_z_c2r(
     constexpr int M = N / 2, K = M + 1;
     using Z = zshape<M, EMAX, THREADS>;
     constexpr int E = Z::E, TPT = Z::TPT, RPB = Z::RPB;
-    __shared__ cx<T> lds[RPB * M];
+    constexpr int PS = first_radix_shift<E>::value, MP = padded_len<M, PS>::value;
+    __shared__ cx<T> lds[RPB * MP];
 
     const int rl = threadIdx.x / TPT;
     const int t = threadIdx.x % TPT;
     const int64_t row = int64_t(blockIdx.x) * RPB + rl;
     const bool valid = row < rows;
-    cx<T>* L = lds + rl * M;
+    const idx_rows<PS> ix{rl * MP};
 
     // Load G[0..M-1] (registers and LDS) and G[M] (thread t = 0), dropping
     // the imaginary parts of kz = 0 and kz = N/2 and applying the bin
@@ -138,7 +141,7 @@ __global__ __launch_bounds__((zshape<N / 2, EMAX, THREADS>::NT)) void k_z_c2r(
         const int k = t + m * TPT;
         if (k == 0) g[m] = cx<T>{g[m].x * mul_edge, T(0)};
         else g[m] = scal(g[m], mul_int);
-        L[k] = g[m];
+        lds[ix.at(xgeom<M, E, 1, 1>::template in_pad<PS>(t, m))] = g[m];
     }
     g_m = cx<T>{g_m.x * mul_edge, T(0)};
     __syncthreads();
@@ -149,13 +152,13 @@ __global__ __launch_bounds__((zshape<N / 2, EMAX, THREADS>::NT)) void k_z_c2r(
 #pragma unroll
     for (int m = 0; m < E; ++m) {
         const int k = t + m * TPT;
-        const cx<T> gc = conjg(k == 0 ? g_m : L[M - k]);
+        const cx<T> gc = conjg(k == 0 ? g_m : lds[ix(M - k)]);
         const cx<T> s = g[m] + gc;
         const cx<T> d = cmulc(g[m] - gc, tw[k]);
         a[m] = cx<T>{s.x - d.y, s.y + d.x};
     }
     __syncthreads();
-    fft_regs<T, M, E, +1>(a, t, tw, 2, xch_full<T, idx_rows>{lds, idx_rows{rl * M}});
+    fft_regs<T, M, E, +1>(a, t, tw, 2, xch_full<T, idx_rows<PS>>{lds, ix});
     if (!valid) return;
     cx<T>* dst = reinterpret_cast<cx<T>*>(out + row * N);
 #pragma unroll
@@ -200,7 +203,10 @@ __global__ __launch_bounds__(TC * N / E) void k_strided(
     constexpr int TPT = N / E;
     constexpr bool SPLIT = XP == 2;
     static_assert(XP == 1 || XP % 2 == 0, "XP must be 1 or even");
-    __shared__ cx<T> lds[(N * TC + XP - 1) / XP];
+    constexpr int PS = XP > 2 ? 0 : first_radix_shift<E>::value;
+    constexpr int NP = padded_len<N, PS>::value;
+    __shared__ cx<T> lds[(NP * TC + XP - 1) / XP];
+    using IX = idx_cols<TC, PS>;
 
     const int c = threadIdx.x % TC;
     const int t = threadIdx.x / TC;
@@ -223,12 +229,12 @@ __global__ __launch_bounds__(TC * N / E) void k_strided(
         }
         if constexpr (XP > 2)
             fft_regs<T, N, E, S>(a, t, tw, 1,
-                                 xch_parts<T, idx_cols<TC>, XP / 2>{reinterpret_cast<T*>(lds), {c}});
+                                 xch_parts<T, IX, XP / 2>{reinterpret_cast<T*>(lds), IX{c}});
         else if constexpr (SPLIT)
             fft_regs<T, N, E, S>(a, t, tw, 1,
-                                 xch_split<T, idx_cols<TC>>{reinterpret_cast<T*>(lds), {c}});
+                                 xch_split<T, IX>{reinterpret_cast<T*>(lds), IX{c}});
         else
-            fft_regs<T, N, E, S>(a, t, tw, 1, xch_full<T, idx_cols<TC>>{lds, {c}});
+            fft_regs<T, N, E, S>(a, t, tw, 1, xch_full<T, IX>{lds, IX{c}});
     } else {
         static_assert(XP <= 2, "MFMA stage: whole or re/im exchange");
         // First radix-16 stage on the matrix cores.  The wave's 64 butterflies
@@ -256,7 +262,7 @@ __global__ __launch_bounds__(TC * N / E) void k_strided(
             dft.run(in, y[g]);
         }
         // exchange: output r of butterfly (c_b, t_b) goes to position 16 t_b + r
-        const idx_cols<TC> pos_c{c};
+        const IX pos_c{c};
         if constexpr (SPLIT) {
             T* buf = reinterpret_cast<T*>(lds);
 #pragma unroll
@@ -265,11 +271,12 @@ __global__ __launch_bounds__(TC * N / E) void k_strided(
                 for (int g = 0; g < 2; ++g)
 #pragma unroll
                     for (int v = 0; v < 8; ++v)
-                        buf[(16 * bt[g] + dft16_out_index(h, v)) * TC + bc[g]] = part ? y[g][v].y : y[g][v].x;
+                        buf[IX{bc[g]}.at(xgeom<N, E, 1, 16>::template out_pad<PS>(bt[g], dft16_out_index(h, v) * (E / 16)))] =
+                            part ? y[g][v].y : y[g][v].x;
                 __syncthreads();
 #pragma unroll
                 for (int i = 0; i < E; ++i) {
-                    const T val = buf[pos_c(t + i * TPT)];
+                    const T val = buf[pos_c.at(xgeom<N, E, 1, 16>::template in_pad<PS>(t, i))];
                     if (part) a[i].y = val; else a[i].x = val;
                 }
                 __syncthreads();
@@ -279,17 +286,17 @@ __global__ __launch_bounds__(TC * N / E) void k_strided(
             for (int g = 0; g < 2; ++g)
 #pragma unroll
                 for (int v = 0; v < 8; ++v)
-                    lds[(16 * bt[g] + dft16_out_index(h, v)) * TC + bc[g]] = y[g][v];
+                    lds[IX{bc[g]}.at(xgeom<N, E, 1, 16>::template out_pad<PS>(bt[g], dft16_out_index(h, v) * (E / 16)))] = y[g][v];
             __syncthreads();
 #pragma unroll
-            for (int i = 0; i < E; ++i) a[i] = lds[pos_c(t + i * TPT)];
+            for (int i = 0; i < E; ++i) a[i] = lds[pos_c.at(xgeom<N, E, 1, 16>::template in_pad<PS>(t, i))];
             __syncthreads();
         }
         if constexpr (SPLIT)
             fft_from<T, N, E, S, 16>(a, t, tw, 1,
-                                     xch_split<T, idx_cols<TC>>{reinterpret_cast<T*>(lds), {c}});
+                                     xch_split<T, IX>{reinterpret_cast<T*>(lds), IX{c}});
         else
-            fft_from<T, N, E, S, 16>(a, t, tw, 1, xch_full<T, idx_cols<TC>>{lds, {c}});
+            fft_from<T, N, E, S, 16>(a, t, tw, 1, xch_full<T, IX>{lds, IX{c}});
     }
     if (!valid) return;
 #pragma unroll
@@ -325,7 +332,7 @@ __global__ __launch_bounds__(kThreads) void k_pack(
 template <typename T, int N>
 static hipError_t z_r2c_n(const void* in, void* out, const void* tw, int64_t rows,
                           row_map map, double me, double mi, hipStream_t s) {
-    using C = zcfg<T, true>;
+    using C = zcfg<T, true, N>;
     using Z = zshape<N / 2, C::EMAX, C::THREADS>;
     const int64_t blocks = (rows + Z::RPB - 1) / Z::RPB;
     if (blocks == 0) return hipSuccess;
@@ -338,7 +345,7 @@ static hipError_t z_r2c_n(const void* in, void* out, const void* tw, int64_t row
 template <typename T, int N>
 static hipError_t z_c2r_n(const void* in, void* out, const void* tw, int64_t rows,
                           row_map map, double me, double mi, hipStream_t s) {
-    using C = zcfg<T, false>;
+    using C = zcfg<T, false, N>;
     using Z = zshape<N / 2, C::EMAX, C::THREADS>;
     const int64_t blocks = (rows + Z::RPB - 1) / Z::RPB;
     if (blocks == 0) return hipSuccess;

@@ -64,7 +64,25 @@ enum {
      * relative error per product about 2^-16 (2 terms) or 2^-24 (3 terms).
      * At most one of the two; GFFT_E_UNSUPPORTED for FP64 or N < 32. */
     GFFT_MFMA_BF16X2 = 1u << 1,
-    GFFT_MFMA_BF16X3 = 1u << 2
+    GFFT_MFMA_BF16X3 = 1u << 2,
+    /* In-place transforms in the FFTW padded layout (the paper counts
+     * Nx/p x Ny x (Nz/2+1) points per GPU before step 1 and shares one work
+     * space between R2C, C2C and C2R, section 3): every real row of N values
+     * is padded to N + 2, so a real row and its K complex bins occupy the
+     * same bytes.  exec_r2c / exec_c2r (and the adjoints and z passes) then
+     * take the SAME pointer for the real and the complex argument, and the
+     * grid needs half the memory.  Not combinable with GFFT_FUSE_PACK (the
+     * send order moves rows); GFFT_E_UNSUPPORTED then. */
+    GFFT_INPLACE = 1u << 3,
+    /* Slab plans: use the paper's chunk order as the exchange wire format.
+     * Step 2 (section 3) transposes the slab to [N][X][K] (ky slowest), so
+     * chunk j is [N/p][X][K] = [ky_l][x_l][kz]; the send buffer is
+     * [p][N/p][X][K] (the standalone pack, or exec_r2c with GFFT_FUSE_PACK).
+     * gfft_exec_x_c2c then takes the received buffer [p][N/p][X][K]
+     * (chunk i from rank i) and folds the chunk transpose of step 4 into its
+     * addressing: line (ky_l, kz) has x = i X + x_l; its result stays in that
+     * buffer order.  GFFT_E_UNSUPPORTED for full-grid plans. */
+    GFFT_PACK_PAPER_ORDER = 1u << 4
 };
 
 typedef struct gfft_plan gfft_plan;
@@ -76,7 +94,7 @@ typedef struct {
     int64_t ranks;         /* p = N / X                                    */
     int64_t batch;         /* independent grids                            */
     int64_t k;             /* K = N/2 + 1                                  */
-    int64_t real_bytes;    /* batch * X * N * N reals                      */
+    int64_t real_bytes;    /* batch * X * N * N reals (N * (N+2) in place) */
     int64_t complex_bytes; /* batch * X * N * K complex (= send buffer)    */
     int64_t pencil_bytes;  /* batch * N * (N/p) * K complex, x-pencil      */
     int64_t chunk_bytes;   /* one all-to-all chunk: X * (N/p) * K complex  */
@@ -91,8 +109,9 @@ typedef struct {
  *            one GPU (p = 1); X < n is rank r's slab of p = n/X ranks
  *            (section 2, slab decomposition).
  *   batch  : >= 1 independent grids per exec call.
- *   flags  : bitwise OR of GFFT_FUSE_PACK and at most one of
- *            GFFT_MFMA_BF16X2 / GFFT_MFMA_BF16X3 (or 0).
+ *   flags  : bitwise OR of GFFT_FUSE_PACK or GFFT_INPLACE,
+ *            GFFT_PACK_PAPER_ORDER, and at most one of GFFT_MFMA_BF16X2 /
+ *            GFFT_MFMA_BF16X3 (or 0).
  * On success *out receives the plan.  The plan owns small device tables
  * (FP64-derived twiddle factors rounded once to the working precision) on
  * the device that is current at creation; exec calls must run with that
@@ -116,7 +135,7 @@ gfft_status gfft_plan_query(const gfft_plan *plan, gfft_plan_sizes *sizes);
  * order.  Slab (X < N): section 3 step 1, the 2D R2C over (y, z) of each
  * local plane; steps 2-4 are the caller's exchange; step 5 is
  * gfft_exec_x_c2c on the received pencil.
- * in_real and out_cplx must not overlap.
+ * in_real and out_cplx must not overlap (must be equal for GFFT_INPLACE).
  */
 gfft_status gfft_exec_r2c(const gfft_plan *plan, const void *in_real,
                           void *out_cplx, void *stream);
@@ -131,7 +150,8 @@ gfft_status gfft_exec_r2c(const gfft_plan *plan, const void *in_real,
  * i.e. the inverse DFT of G's Hermitian extension.
  *   in_cplx  : [batch][X][N][K] complex (send order with GFFT_FUSE_PACK).
  *              CLOBBERED: the y (and x) passes run in place on it.
- *   out_real : [batch][X][N][N] reals.  Must not overlap in_cplx.
+ *   out_real : [batch][X][N][N] reals.  Must not overlap in_cplx (must be
+ *              equal to it for GFFT_INPLACE, rows then padded to N + 2).
  * Slab plans run the inverse of step 1 only (see gfft_exec_r2c).
  */
 gfft_status gfft_exec_c2r(const gfft_plan *plan, void *in_cplx,

@@ -26,6 +26,8 @@ GFFT_F32 = 1
 GFFT_FUSE_PACK = 1 << 0
 GFFT_MFMA_BF16X2 = 1 << 1
 GFFT_MFMA_BF16X3 = 1 << 2
+GFFT_INPLACE = 1 << 3
+GFFT_PACK_PAPER_ORDER = 1 << 4
 
 # Every symbol include/gfft.h declares.
 EXPORTS = (

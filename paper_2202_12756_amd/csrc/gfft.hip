@@ -13,6 +13,7 @@
 
 struct gfft_plan {
     int64_t n, x, p, y, batch, k;
+    int64_t rs;  // reals between real rows: n, or n + 2 in place
     int lg_n, lg_x, lg_y, lg_p;
     gfft_dtype dtype;
     uint32_t flags;
@@ -22,7 +23,8 @@ struct gfft_plan {
 
 namespace {
 
-constexpr uint32_t kKnownFlags = GFFT_FUSE_PACK | GFFT_MFMA_BF16X2 | GFFT_MFMA_BF16X3;
+constexpr uint32_t kKnownFlags =
+    GFFT_FUSE_PACK | GFFT_MFMA_BF16X2 | GFFT_MFMA_BF16X3 | GFFT_INPLACE | GFFT_PACK_PAPER_ORDER;
 
 int ilog2(int64_t v) {
     int l = 0;
@@ -73,34 +75,63 @@ bool overlap(const void* a, int64_t na, const void* b, int64_t nb) {
     return x < y + uint64_t(nb) && y < x + uint64_t(na);
 }
 
-int64_t real_size(const gfft_plan* p) { return p->batch * p->x * p->n * p->n; }
+int64_t real_size(const gfft_plan* p) { return p->batch * p->x * p->n * p->rs; }
 int64_t cplx_count(const gfft_plan* p) { return p->batch * p->x * p->n * p->k; }
 int64_t elt(const gfft_plan* p) { return p->dtype == GFFT_F64 ? 8 : 4; }
 int64_t real_bytes(const gfft_plan* p) { return real_size(p) * elt(p); }
 int64_t cplx_bytes(const gfft_plan* p) { return cplx_count(p) * 2 * elt(p); }
 
+bool paper(const gfft_plan* p) { return (p->flags & GFFT_PACK_PAPER_ORDER) != 0; }
+
+// Rows of the half spectrum that the z passes write or read: natural, or one
+// of the two send orders when the pack is fused.
 gfft::row_map zmap(const gfft_plan* p) {
     const bool packed = (p->flags & GFFT_FUSE_PACK) != 0;
-    return gfft::row_map{p->lg_n, p->lg_x, packed ? p->lg_y : p->lg_n};
+    return gfft::row_map{p->lg_n, p->lg_x, packed ? p->lg_y : p->lg_n, p->rs,
+                         packed && paper(p) ? 1 : 0};
 }
 
-// y lines of a [batch][X][N][K] half spectrum, natural or send order.
+// The send order of the standalone pack.
+gfft::row_map packmap(const gfft_plan* p) {
+    return gfft::row_map{p->lg_n, p->lg_x, p->lg_y, p->rs, paper(p) ? 1 : 0};
+}
+
+// y lines of a [batch][X][N][K] half spectrum: natural, send order
+// [p][X][N/p][K], or the paper's order [N][X][K] (slab transposed).
 gfft::line_map ymap(const gfft_plan* p) {
     const bool packed = (p->flags & GFFT_FUSE_PACK) != 0;
-    const int64_t yy = packed ? p->y : p->n;
     gfft::line_map lm;
     lm.b_hi = p->x * p->n * p->k;
+    lm.lg_bx = p->lg_x;
+    if (packed && paper(p)) {
+        lm.b_lo = p->k;
+        lm.s_hi = 0;
+        lm.s_lo = p->x * p->k;
+        lm.lg_y = p->lg_n;
+        return lm;
+    }
+    const int64_t yy = packed ? p->y : p->n;
     lm.b_lo = yy * p->k;
     lm.s_hi = p->x * yy * p->k;
     lm.s_lo = p->k;
-    lm.lg_bx = p->lg_x;
     lm.lg_y = packed ? p->lg_y : p->lg_n;
     return lm;
 }
 
-// x lines of a [batch][N][Y][K] pencil.
+// x lines of a received pencil: [batch][N][Y][K] (x = i X + x_l slowest), or
+// in the paper's chunk order [batch][p][Y][X][K] with the chunk transpose of
+// step 4 folded into the addressing (a batch of Y line sets, K columns each).
 gfft::line_map xmap(const gfft_plan* p) {
     gfft::line_map lm;
+    if (paper(p)) {
+        lm.b_hi = p->n * p->y * p->k;
+        lm.b_lo = p->x * p->k;
+        lm.lg_bx = p->lg_y;
+        lm.s_hi = p->y * p->x * p->k;
+        lm.s_lo = p->k;
+        lm.lg_y = p->lg_x;
+        return lm;
+    }
     lm.b_hi = p->n * p->y * p->k;
     lm.b_lo = 0;
     lm.s_hi = 0;
@@ -142,16 +173,21 @@ gfft_status run_y(const gfft_plan* p, void* data, int sign, hipStream_t s) {
 }
 
 gfft_status run_x(const gfft_plan* p, void* data, int sign, hipStream_t s) {
+    const int64_t cols = paper(p) ? p->k : p->y * p->k;
+    const int64_t sets = paper(p) ? p->batch * p->y : p->batch;
     return hip_status(gfft::launch_strided(f64(p), int(p->n), 1, mfma_terms(p), sign, data,
-                                           p->tw, p->y * p->k, p->batch, xmap(p), s));
+                                           p->tw, cols, sets, xmap(p), s));
 }
 
-gfft_status check_r2c_args(const gfft_plan* p, const void* in, const void* out) {
+// `real` and `cplx` are the two buffers of a z pass: distinct and disjoint,
+// or the very same buffer for an in-place plan.
+gfft_status check_r2c_args(const gfft_plan* p, const void* real, const void* cplx) {
     if (!p) return GFFT_E_INVALID_ARG;
-    gfft_status st = check_ptr(in);
+    gfft_status st = check_ptr(real);
     if (st != GFFT_OK) return st;
-    if ((st = check_ptr(out)) != GFFT_OK) return st;
-    if (overlap(in, real_bytes(p), out, cplx_bytes(p))) return GFFT_E_INVALID_ARG;
+    if ((st = check_ptr(cplx)) != GFFT_OK) return st;
+    if (p->flags & GFFT_INPLACE) return real == cplx ? GFFT_OK : GFFT_E_INVALID_ARG;
+    if (overlap(real, real_bytes(p), cplx, cplx_bytes(p))) return GFFT_E_INVALID_ARG;
     return GFFT_OK;
 }
 
@@ -209,6 +245,8 @@ gfft_status gfft_plan_create(gfft_plan** out, int64_t n, gfft_dtype dtype, int64
     const uint32_t mf = flags & (GFFT_MFMA_BF16X2 | GFFT_MFMA_BF16X3);
     if (mf == (GFFT_MFMA_BF16X2 | GFFT_MFMA_BF16X3)) return GFFT_E_INVALID_ARG;
     if (mf && (dtype != GFFT_F32 || n < 32)) return GFFT_E_UNSUPPORTED;
+    if ((flags & GFFT_INPLACE) && (flags & GFFT_FUSE_PACK)) return GFFT_E_UNSUPPORTED;
+    if ((flags & GFFT_PACK_PAPER_ORDER) && slab_x == n) return GFFT_E_UNSUPPORTED;
     // sizes must stay addressable with 64-bit element offsets
     const int64_t k = n / 2 + 1;
     if (batch > (int64_t(1) << 62) / (slab_x * n * k * 2 * 8)) return GFFT_E_UNSUPPORTED;
@@ -229,6 +267,7 @@ gfft_status gfft_plan_create(gfft_plan** out, int64_t n, gfft_dtype dtype, int64
     p->y = n / p->p;
     p->batch = batch;
     p->k = k;
+    p->rs = (flags & GFFT_INPLACE) ? n + 2 : n;
     p->lg_n = ilog2(n);
     p->lg_x = ilog2(slab_x);
     p->lg_p = ilog2(p->p);
@@ -314,6 +353,9 @@ gfft_status gfft_pack_slab_for_alltoall(const gfft_plan* p, const void* src, voi
     gfft_status st = check_ptr(src);
     if (st != GFFT_OK || (st = check_ptr(dst)) != GFFT_OK) return st;
     if (overlap(src, cplx_bytes(p), dst, cplx_bytes(p))) return GFFT_E_INVALID_ARG;
+    if (paper(p))
+        return hip_status(gfft::launch_pack_rows(f64(p), src, dst, p->batch * p->x * p->n, p->k,
+                                                 packmap(p), true, as_stream(stream)));
     return hip_status(gfft::launch_pack(f64(p), src, dst, p->batch * p->p * p->x, p->lg_x,
                                         p->lg_p, p->n, p->y, p->k, true, as_stream(stream)));
 }
@@ -324,6 +366,9 @@ gfft_status gfft_unpack_slab_from_alltoall(const gfft_plan* p, const void* src, 
     gfft_status st = check_ptr(src);
     if (st != GFFT_OK || (st = check_ptr(dst)) != GFFT_OK) return st;
     if (overlap(src, cplx_bytes(p), dst, cplx_bytes(p))) return GFFT_E_INVALID_ARG;
+    if (paper(p))
+        return hip_status(gfft::launch_pack_rows(f64(p), src, dst, p->batch * p->x * p->n, p->k,
+                                                 packmap(p), false, as_stream(stream)));
     return hip_status(gfft::launch_pack(f64(p), src, dst, p->batch * p->p * p->x, p->lg_x,
                                         p->lg_p, p->n, p->y, p->k, false, as_stream(stream)));
 }

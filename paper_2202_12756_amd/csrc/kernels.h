@@ -10,8 +10,15 @@ namespace gfft {
 // z-line) to the row it occupies in a half-spectrum buffer: the natural row
 // when lg_y == lg_n, or the all-to-all send order [p][X][N/p] of the slab's
 // chunks (chunk j = y / (N/p)) otherwise.  All extents are powers of two.
+// rs is the distance between real rows, in reals: N, or N + 2 for the
+// padded rows of an in-place transform (a real row and its K complex bins
+// then share the same bytes).
+// paper != 0 selects the chunk order of the paper's local xy transpose,
+// [p][N/p][X] = the slab transposed to [N][X] (row (x_l, y) at y X + x_l).
 struct row_map {
     int lg_n, lg_x, lg_y;
+    int64_t rs;
+    int paper;
 };
 
 // Address of element (b, n, m) of a batch of strided lines:
@@ -45,5 +52,10 @@ hipError_t launch_strided(bool f64, int n, int axis, int mfma_terms, int sign, v
 hipError_t launch_pack(bool f64, const void* src, void* dst, int64_t chunks,
                        int lg_x, int lg_p, int64_t n, int64_t y, int64_t k,
                        bool to_send, hipStream_t s);
+// Copy `rows` rows of k complex values between the natural order and the
+// order `map` describes (natural row r <-> map_row(r)), to_send choosing the
+// direction.  Used for the paper's chunk order, whose rows interleave.
+hipError_t launch_pack_rows(bool f64, const void* src, void* dst, int64_t rows, int64_t k,
+                            row_map map, bool to_send, hipStream_t s);
 
 }  // namespace gfft

@@ -26,6 +26,7 @@ __device__ __forceinline__ int64_t map_row(int64_t r, row_map m) {
     const int64_t y = r & ((int64_t(1) << m.lg_n) - 1);
     const int64_t b = bx >> m.lg_x;
     const int64_t xl = bx & ((int64_t(1) << m.lg_x) - 1);
+    if (m.paper) return (b << (m.lg_x + m.lg_n)) + (y << m.lg_x) + xl;
     const int64_t j = y >> m.lg_y;
     const int64_t yl = y & ((int64_t(1) << m.lg_y) - 1);
     return (b << (m.lg_x + m.lg_n)) + ((((j << m.lg_x) + xl)) << m.lg_y) + yl;
@@ -60,9 +61,10 @@ struct zcfg {
 };
 
 // ---------------------------------------------------------------- z R2C
-template <typename T, int N, int EMAX = 16, int THREADS = kThreads>
+template <typename T, int N, int EMAX = 16, int THREADS = kThreads, bool REMAP = false,
+          bool NTS = false>
 __global__ __launch_bounds__((zshape<N / 2, EMAX, THREADS>::NT)) void k_z_r2c(
-    const T* __restrict__ in, cx<T>* __restrict__ out, const cx<T>* __restrict__ tw,
+    const T* in, cx<T>* out, const cx<T>* __restrict__ tw,
     int64_t rows, row_map map, T mul_edge, T mul_int) {
     constexpr int M = N / 2, K = M + 1;
     using Z = zshape<M, EMAX, THREADS>;
@@ -72,10 +74,11 @@ __global__ __launch_bounds__((zshape<N / 2, EMAX, THREADS>::NT)) void k_z_r2c(
 
     const int rl = threadIdx.x / TPT;
     const int t = threadIdx.x % TPT;
-    const int64_t row = int64_t(blockIdx.x) * RPB + rl;
+    const int64_t blk = REMAP ? xcd_tile(blockIdx.x, gridDim.x) : int64_t(blockIdx.x);
+    const int64_t row = blk * RPB + rl;
     const bool valid = row < rows;
 
-    const cx<T>* src = reinterpret_cast<const cx<T>*>(in + row * N);
+    const cx<T>* src = reinterpret_cast<const cx<T>*>(in + row * map.rs);
     cx<T> a[E];
 #pragma unroll
     for (int m = 0; m < E; ++m) a[m] = valid ? src[t + m * TPT] : cx<T>{T(0), T(0)};
@@ -100,15 +103,22 @@ __global__ __launch_bounds__((zshape<N / 2, EMAX, THREADS>::NT)) void k_z_r2c(
         const cx<T> B = scal(zk - zc, T(0.5));
         const cx<T> wb = cmul(tw[k], B);
         const T f = k == 0 ? mul_edge : mul_int;
-        dst[k] = cx<T>{(A.x + wb.y) * f, (A.y - wb.x) * f};
+        const cx<T> v{(A.x + wb.y) * f, (A.y - wb.x) * f};
+        if constexpr (NTS) {
+            __builtin_nontemporal_store(v.x, &dst[k].x);
+            __builtin_nontemporal_store(v.y, &dst[k].y);
+        } else {
+            dst[k] = v;
+        }
     }
     if (t == 0) dst[M] = cx<T>{(a[0].x - a[0].y) * mul_edge, T(0)};
 }
 
 // ---------------------------------------------------------------- z C2R
-template <typename T, int N, int EMAX = 16, int THREADS = kThreads>
+template <typename T, int N, int EMAX = 16, int THREADS = kThreads, bool REMAP = false,
+          bool NTS = false>
 __global__ __launch_bounds__((zshape<N / 2, EMAX, THREADS>::NT)) void k_z_c2r(
-    const cx<T>* __restrict__ in, T* __restrict__ out, const cx<T>* __restrict__ tw,
+    const cx<T>* in, T* out, const cx<T>* __restrict__ tw,
     int64_t rows, row_map map, T mul_edge, T mul_int) {
     constexpr int M = N / 2, K = M + 1;
     using Z = zshape<M, EMAX, THREADS>;
@@ -118,7 +128,8 @@ __global__ __launch_bounds__((zshape<N / 2, EMAX, THREADS>::NT)) void k_z_c2r(
 
     const int rl = threadIdx.x / TPT;
     const int t = threadIdx.x % TPT;
-    const int64_t row = int64_t(blockIdx.x) * RPB + rl;
+    const int64_t blk = REMAP ? xcd_tile(blockIdx.x, gridDim.x) : int64_t(blockIdx.x);
+    const int64_t row = blk * RPB + rl;
     const bool valid = row < rows;
     const idx_rows<PS> ix{rl * MP};
 
@@ -160,9 +171,16 @@ __global__ __launch_bounds__((zshape<N / 2, EMAX, THREADS>::NT)) void k_z_c2r(
     __syncthreads();
     fft_regs<T, M, E, +1>(a, t, tw, 2, xch_full<T, idx_rows<PS>>{lds, ix});
     if (!valid) return;
-    cx<T>* dst = reinterpret_cast<cx<T>*>(out + row * N);
+    cx<T>* dst = reinterpret_cast<cx<T>*>(out + row * map.rs);
 #pragma unroll
-    for (int m = 0; m < E; ++m) dst[t + m * TPT] = a[m];
+    for (int m = 0; m < E; ++m) {
+        if constexpr (NTS) {
+            __builtin_nontemporal_store(a[m].x, &dst[t + m * TPT].x);
+            __builtin_nontemporal_store(a[m].y, &dst[t + m * TPT].y);
+        } else {
+            dst[t + m * TPT] = a[m];
+        }
+    }
 }
 
 // ---------------------------------------------------------------- y / x C2C
@@ -328,6 +346,23 @@ __global__ __launch_bounds__(kThreads) void k_pack(
     for (int64_t e = part * kThreads + threadIdx.x; e < len; e += step) d[e] = s[e];
 }
 
+// Row permutation copy: workgroup copies kRows rows, k values each.
+constexpr int kPackRows = 4;
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_pack_rows(
+    const cx<T>* __restrict__ src, cx<T>* __restrict__ dst, int64_t rows, int64_t k,
+    row_map map, bool to_send) {
+#pragma unroll
+    for (int i = 0; i < kPackRows; ++i) {
+        const int64_t r = int64_t(blockIdx.x) * kPackRows + i;
+        if (r >= rows) return;
+        const int64_t q = map_row(r, map);
+        const cx<T>* s = src + (to_send ? r : q) * k;
+        cx<T>* d = dst + (to_send ? q : r) * k;
+        for (int64_t e = threadIdx.x; e < k; e += kThreads) d[e] = s[e];
+    }
+}
+
 // ---------------------------------------------------------------- launchers
 template <typename T, int N>
 static hipError_t z_r2c_n(const void* in, void* out, const void* tw, int64_t rows,
@@ -440,6 +475,21 @@ hipError_t launch_pack(bool f64, const void* src, void* dst, int64_t chunks, int
         hipLaunchKernelGGL((k_pack<float>), dim3(blocks), dim3(kThreads), 0, s,
                            static_cast<const cx<float>*>(src), static_cast<cx<float>*>(dst),
                            len, bpc, lg_x, lg_p, n, y, k, to_send);
+    return hipGetLastError();
+}
+
+hipError_t launch_pack_rows(bool f64, const void* src, void* dst, int64_t rows, int64_t k,
+                            row_map map, bool to_send, hipStream_t s) {
+    const int64_t blocks = (rows + kPackRows - 1) / kPackRows;
+    if (blocks == 0 || k == 0) return hipSuccess;
+    if (f64)
+        hipLaunchKernelGGL((k_pack_rows<double>), dim3(blocks), dim3(kThreads), 0, s,
+                           static_cast<const cx<double>*>(src), static_cast<cx<double>*>(dst),
+                           rows, k, map, to_send);
+    else
+        hipLaunchKernelGGL((k_pack_rows<float>), dim3(blocks), dim3(kThreads), 0, s,
+                           static_cast<const cx<float>*>(src), static_cast<cx<float>*>(dst),
+                           rows, k, map, to_send);
     return hipGetLastError();
 }
 

@@ -26,12 +26,18 @@ class Plan:
     ``fuse_pack``; x-pencil [batch, N, N/p, K].  For batch == 1 the leading
     batch dimension may be omitted.  ``mfma_terms`` (FP32 only) runs the first
     radix-16 stage of the y and x passes on the matrix cores with 2 or 3
-    BF16 terms per operand.
+    BF16 terms per operand.  ``inplace`` plans transform one shared buffer
+    (a complex [batch, X, N, K] tensor whose real view holds rows of N reals
+    padded to N + 2): use ``empty_inplace``, ``real_view``, ``r2c_`` and
+    ``c2r_``.  ``paper_order`` uses the paper's chunk order [ky_l][x_l][kz]
+    as the exchange format (send buffer and received pencil
+    [batch, p, N/p, X, K]).
     """
 
     def __init__(self, n: int, dtype=torch.float64, slab_x: int | None = None,
                  batch: int = 1, fuse_pack: bool = False, device=None,
-                 mfma_terms: int = 0):
+                 mfma_terms: int = 0, inplace: bool = False,
+                 paper_order: bool = False):
         if dtype not in _REAL:
             raise TypeError("dtype must be torch.float64 or torch.float32")
         self.n = int(n)
@@ -42,7 +48,13 @@ class Plan:
         self.fuse_pack = bool(fuse_pack)
         self.device = torch.device(device if device is not None else "cuda")
         self.mfma_terms = int(mfma_terms)
+        self.inplace = bool(inplace)
+        self.paper_order = bool(paper_order)
         flags = _lib.GFFT_FUSE_PACK if fuse_pack else 0
+        if self.inplace:
+            flags |= _lib.GFFT_INPLACE
+        if self.paper_order:
+            flags |= _lib.GFFT_PACK_PAPER_ORDER
         if self.mfma_terms not in (0, 2, 3):
             raise ValueError("mfma_terms must be 0, 2 or 3")
         if self.mfma_terms == 2:
@@ -68,18 +80,22 @@ class Plan:
     @property
     def spectrum_shape(self):
         if self.fuse_pack:
-            return (self.batch, self.ranks, self.slab_x, self.n // self.ranks,
-                    self.k)
+            return self.send_shape
         return (self.batch, self.slab_x, self.n, self.k)
 
     @property
     def send_shape(self):
-        return (self.batch, self.ranks, self.slab_x, self.n // self.ranks,
-                self.k)
+        y = self.n // self.ranks
+        if self.paper_order:      # chunk j = [ky_l][x_l][kz]
+            return (self.batch, self.ranks, y, self.slab_x, self.k)
+        return (self.batch, self.ranks, self.slab_x, y, self.k)
 
     @property
     def pencil_shape(self):
-        return (self.batch, self.n, self.n // self.ranks, self.k)
+        y = self.n // self.ranks
+        if self.paper_order:      # received chunks [i][ky_l][x_l][kz]
+            return (self.batch, self.ranks, y, self.slab_x, self.k)
+        return (self.batch, self.n, y, self.k)
 
     def _check(self, t: torch.Tensor, dtype, numel: int, what: str):
         if not isinstance(t, torch.Tensor):
@@ -97,7 +113,8 @@ class Plan:
         return t.data_ptr()
 
     def _nreal(self):
-        return self.batch * self.slab_x * self.n * self.n
+        rs = self.n + 2 if self.inplace else self.n
+        return self.batch * self.slab_x * self.n * rs
 
     def _ncplx(self):
         return self.batch * self.slab_x * self.n * self.k
@@ -177,6 +194,47 @@ class Plan:
         _lib.check(_lib.gfft_exec_x_c2c(self._h, a, int(sign),
                                         _stream(self.device)), "gfft_exec_x_c2c")
         return pencil
+
+    # ------------------------------------------------------------ in place
+    def empty_inplace(self):
+        """The shared buffer of an in-place plan (complex, spectrum shape)."""
+        return torch.empty((self.batch, self.slab_x, self.n, self.k),
+                           dtype=self.cdtype, device=self.device)
+
+    def real_view(self, buf: torch.Tensor) -> torch.Tensor:
+        """The [batch, X, N, N] real field inside a padded shared buffer."""
+        r = torch.view_as_real(buf).reshape(self.batch, self.slab_x, self.n, 2 * self.k)
+        return r[..., : self.n]
+
+    def _inplace_ptr(self, buf):
+        if not self.inplace:
+            raise ValueError("plan was not created with inplace=True")
+        return self._check(buf, self.cdtype, self._ncplx(), "buffer")
+
+    def r2c_(self, buf: torch.Tensor):
+        """In-place forward transform of the padded field in ``buf``."""
+        a = self._inplace_ptr(buf)
+        _lib.check(_lib.gfft_exec_r2c(self._h, a, a, _stream(self.device)), "gfft_exec_r2c")
+        return buf
+
+    def c2r_(self, buf: torch.Tensor, scale: float = 1.0):
+        """In-place inverse; returns the real view of ``buf``."""
+        a = self._inplace_ptr(buf)
+        _lib.check(_lib.gfft_exec_c2r(self._h, a, a, float(scale), _stream(self.device)),
+                   "gfft_exec_c2r")
+        return self.real_view(buf)
+
+    def r2c_adjoint_(self, buf: torch.Tensor, scale: float = 1.0):
+        a = self._inplace_ptr(buf)
+        _lib.check(_lib.gfft_exec_r2c_adjoint(self._h, a, a, float(scale),
+                                              _stream(self.device)), "gfft_exec_r2c_adjoint")
+        return self.real_view(buf)
+
+    def c2r_adjoint_(self, buf: torch.Tensor, scale: float = 1.0):
+        a = self._inplace_ptr(buf)
+        _lib.check(_lib.gfft_exec_c2r_adjoint(self._h, a, a, float(scale),
+                                              _stream(self.device)), "gfft_exec_c2r_adjoint")
+        return buf
 
     # ------------------------------------------------------------ passes
     def z_r2c(self, x, out=None, scale: float = 1.0, weighted: bool = False):

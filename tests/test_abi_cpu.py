@@ -56,6 +56,10 @@ def test_status_strings_and_version():
     ((64, 0, 64, 1, 2), _lib.GFFT_E_UNSUPPORTED),              # MFMA needs FP32
     ((16, 1, 16, 1, 4), _lib.GFFT_E_UNSUPPORTED),              # MFMA needs N >= 32
     ((64, 1, 64, 1, 6), _lib.GFFT_E_INVALID_ARG),              # both MFMA flags
+    ((64, 0, 64, 1, 8), None),                                 # in place
+    ((64, 0, 16, 1, 9), _lib.GFFT_E_UNSUPPORTED),              # in place + send order
+    ((64, 0, 16, 1, 17), None),                                # paper chunk order, fused
+    ((64, 0, 64, 1, 16), _lib.GFFT_E_UNSUPPORTED),             # paper order needs a slab
 ])
 def test_plan_create_validates_on_host(args, expect):
     st, h = _lib.gfft_plan_create(*args)

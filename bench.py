@@ -149,6 +149,9 @@ def variants(n: int, steps: int, x64: torch.Tensor, dev) -> dict:
     first radix-16 stage of the y and x passes on the matrix cores (2 or 3
     BF16 terms per operand); each forward spectrum is compared with the FP64
     path's on the same GPU.
+    slab_pack_p8_f64: the slab transpose (the paper's steps 2-4) for rank 0
+    of 8: the standalone pack into 8 send chunks, and the local 2D R2C with
+    and without the pack fused into the z pass's stores.
     adjoint_f64: the gradient pair of a loss through both transforms,
     C2R^T (scale w R2C) then R2C^T (C2R(G/w)), on the FP64 input.
     """
@@ -180,6 +183,29 @@ def variants(n: int, steps: int, x64: torch.Tensor, dev) -> dict:
         del F32, y32, p32
         torch.cuda.empty_cache()
     del x32, F64
+    torch.cuda.empty_cache()
+    # the slab transpose of steps 2-4 at p = 8 (X = N/8 planes): the standalone
+    # pack, and step 1 with and without the pack fused into its stores
+    ranks = 8
+    ps = Plan(n, torch.float64, slab_x=n // ranks, device=dev)
+    pf = Plan(n, torch.float64, slab_x=n // ranks, fuse_pack=True, device=dev)
+    xs = x64[0, : n // ranks].contiguous()
+    S = ps.r2c(xs)
+    send = torch.empty(ps.send_shape, dtype=torch.complex128, device=dev)
+    ms_pack = time_pairs(lambda: ps.pack(S, send), steps, 2)
+    ms_unfused = time_pairs(lambda: (ps.r2c(xs, S), ps.pack(S, send)), steps, 2)
+    send2 = torch.empty_like(send)
+    ms_fused = time_pairs(lambda: pf.r2c(xs, send2), steps, 2)
+    cs = S.numel() * 16
+    out["slab_pack_p8_f64"] = {
+        "chunk": f"{n // ranks}x{n // ranks}x{k}",
+        "pack_ms": round(ms_pack, 4),
+        "pack_GBps": round(2 * cs / (ms_pack * 1e-3) / 1e9, 1),
+        "r2c2d_then_pack_ms": round(ms_unfused, 4),
+        "r2c2d_fused_pack_ms": round(ms_fused, 4),
+        "fused_equals_standalone": bool(torch.equal(send, send2)),
+    }
+    del ps, pf, xs, S, send, send2
     torch.cuda.empty_cache()
     # adjoint pair in FP64
     G = p64.empty_spectrum()

@@ -369,6 +369,9 @@ __global__ __launch_bounds__(kThreads) void k_pack_rows(
 }
 
 // ---------------------------------------------------------------- launchers
+// Grids are one-dimensional; refuse block counts a dim3 cannot hold.
+constexpr int64_t kMaxBlocks = 0x7fffffff;
+
 template <typename T, int N>
 static hipError_t z_r2c_n(const void* in, void* out, const void* tw, int64_t rows,
                           row_map map, double me, double mi, hipStream_t s) {
@@ -376,6 +379,7 @@ static hipError_t z_r2c_n(const void* in, void* out, const void* tw, int64_t row
     using Z = zshape<N / 2, C::EMAX, C::THREADS>;
     const int64_t blocks = (rows + Z::RPB - 1) / Z::RPB;
     if (blocks == 0) return hipSuccess;
+    if (blocks > kMaxBlocks) return hipErrorInvalidValue;
     hipLaunchKernelGGL((k_z_r2c<T, N, C::EMAX, C::THREADS, C::REMAP, C::NTS>), dim3(blocks), dim3(Z::NT), 0, s,
                        static_cast<const T*>(in), static_cast<cx<T>*>(out),
                        static_cast<const cx<T>*>(tw), rows, map, T(me), T(mi));
@@ -389,6 +393,7 @@ static hipError_t z_c2r_n(const void* in, void* out, const void* tw, int64_t row
     using Z = zshape<N / 2, C::EMAX, C::THREADS>;
     const int64_t blocks = (rows + Z::RPB - 1) / Z::RPB;
     if (blocks == 0) return hipSuccess;
+    if (blocks > kMaxBlocks) return hipErrorInvalidValue;
     hipLaunchKernelGGL((k_z_c2r<T, N, C::EMAX, C::THREADS, C::REMAP, C::NTS>), dim3(blocks), dim3(Z::NT), 0, s,
                        static_cast<const cx<T>*>(in), static_cast<T*>(out),
                        static_cast<const cx<T>*>(tw), rows, map, T(me), T(mi));
@@ -403,6 +408,7 @@ static hipError_t strided_ax(int sign, void* data, const void* tw, int64_t m_col
     const int64_t tiles_m = (m_cols + TC - 1) / TC;
     const int64_t blocks = tiles_m * n_b;
     if (blocks == 0) return hipSuccess;
+    if (blocks > kMaxBlocks) return hipErrorInvalidValue;
     const dim3 threads(TC * SH::TPT);
     if (sign < 0)
         hipLaunchKernelGGL((k_strided<T, N, TC, SH::XP, -1, SH::E, MF>), dim3(blocks), threads,
@@ -472,6 +478,7 @@ hipError_t launch_pack(bool f64, const void* src, void* dst, int64_t chunks, int
     if (bpc < 1) bpc = 1;
     const int64_t blocks = chunks * bpc;
     if (blocks == 0 || len == 0) return hipSuccess;
+    if (blocks > kMaxBlocks) return hipErrorInvalidValue;
     if (f64)
         hipLaunchKernelGGL((k_pack<double>), dim3(blocks), dim3(kThreads), 0, s,
                            static_cast<const cx<double>*>(src), static_cast<cx<double>*>(dst),
@@ -487,6 +494,7 @@ hipError_t launch_pack_rows(bool f64, const void* src, void* dst, int64_t rows, 
                             row_map map, bool to_send, hipStream_t s) {
     const int64_t blocks = (rows + kPackRows - 1) / kPackRows;
     if (blocks == 0 || k == 0) return hipSuccess;
+    if (blocks > kMaxBlocks) return hipErrorInvalidValue;
     if (f64)
         hipLaunchKernelGGL((k_pack_rows<double>), dim3(blocks), dim3(kThreads), 0, s,
                            static_cast<const cx<double>*>(src), static_cast<cx<double>*>(dst),

@@ -54,21 +54,24 @@ struct zshape {
 // 4096^2 rows: FP64 R2C 8 elements per thread (16 for N >= 2048) in
 // 256-thread workgroups, FP64 C2R 16 per thread in 64-thread workgroups,
 // FP32 32 per thread in 64-thread ones.
-// Workgroups are dealt to XCDs in contiguous ranges (4-5% faster in FP64);
-// the C2R's aligned real rows are stored non-temporally (they are not read
-// again soon), which the R2C's unaligned complex rows do not gain from.
+// The C2R deals its workgroups to XCDs in contiguous ranges and stores its
+// aligned real rows non-temporally (they are not read again soon): 3-5%
+// faster in FP64.  The R2C, whose complex rows are not line-aligned, gains
+// from neither (the XCD order cost FP32 15%), so it keeps the plain order.
 template <typename T, bool FWD, int N>
 struct zcfg {
     static constexpr int EMAX = sizeof(T) == 8 ? (FWD ? (N >= 2048 ? 16 : 8) : 16) : 32;
     static constexpr int THREADS = sizeof(T) == 8 && FWD ? 256 : 64;
-    static constexpr bool REMAP = true;
+    static constexpr bool REMAP = !FWD;
     static constexpr bool NTS = !FWD;
 };
 
 // ---------------------------------------------------------------- z R2C
-template <typename T, int N, int EMAX = 16, int THREADS = kThreads, bool REMAP = false,
-          bool NTS = false>
-__global__ __launch_bounds__((zshape<N / 2, EMAX, THREADS>::NT)) void k_z_r2c(
+// ALIAS: `in` and `out` are the same buffer (in-place plans).  Each row is
+// read completely before the first barrier and written after the last one,
+// so a row is never overwritten before all of it has been loaded.
+template <typename T, int N, int EMAX, int THREADS, bool REMAP, bool NTS, bool ALIAS>
+__device__ __forceinline__ void z_r2c_body(
     const T* in, cx<T>* out, const cx<T>* __restrict__ tw,
     int64_t rows, row_map map, T mul_edge, T mul_int) {
     constexpr int M = N / 2, K = M + 1;
@@ -98,7 +101,19 @@ __global__ __launch_bounds__((zshape<N / 2, EMAX, THREADS>::NT)) void k_z_r2c(
     for (int m = 0; m < E; ++m) lds[ix.at(xgeom<M, E, 1, 1>::template in_pad<PS>(t, m))] = a[m];
     __syncthreads();
     if (!valid) return;
+    // With ALIAS, all bins are formed in registers before the first store:
+    // stores through a pointer that may alias `in` would otherwise keep the
+    // twiddle loads from being issued early.
+    const cx<T> x_m{(a[0].x - a[0].y) * mul_edge, T(0)};
     cx<T>* dst = out + map_row(row, map) * K;
+    auto put = [&](int k, cx<T> v) {
+        if constexpr (NTS) {
+            __builtin_nontemporal_store(v.x, &dst[k].x);
+            __builtin_nontemporal_store(v.y, &dst[k].y);
+        } else {
+            dst[k] = v;
+        }
+    };
 #pragma unroll
     for (int m = 0; m < E; ++m) {
         const int k = t + m * TPT;
@@ -109,20 +124,33 @@ __global__ __launch_bounds__((zshape<N / 2, EMAX, THREADS>::NT)) void k_z_r2c(
         const cx<T> wb = cmul(tw[k], B);
         const T f = k == 0 ? mul_edge : mul_int;
         const cx<T> v{(A.x + wb.y) * f, (A.y - wb.x) * f};
-        if constexpr (NTS) {
-            __builtin_nontemporal_store(v.x, &dst[k].x);
-            __builtin_nontemporal_store(v.y, &dst[k].y);
-        } else {
-            dst[k] = v;
-        }
+        if constexpr (ALIAS) a[m] = v;
+        else put(k, v);
     }
-    if (t == 0) dst[M] = cx<T>{(a[0].x - a[0].y) * mul_edge, T(0)};
+    if constexpr (ALIAS) {
+#pragma unroll
+        for (int m = 0; m < E; ++m) put(t + m * TPT, a[m]);
+    }
+    if (t == 0) dst[M] = x_m;
+}
+
+template <typename T, int N, int EMAX, int THREADS, bool REMAP, bool NTS>
+__global__ __launch_bounds__((zshape<N / 2, EMAX, THREADS>::NT)) void k_z_r2c(
+    const T* __restrict__ in, cx<T>* __restrict__ out, const cx<T>* __restrict__ tw,
+    int64_t rows, row_map map, T mul_edge, T mul_int) {
+    z_r2c_body<T, N, EMAX, THREADS, REMAP, NTS, false>(in, out, tw, rows, map, mul_edge, mul_int);
+}
+
+template <typename T, int N, int EMAX, int THREADS, bool REMAP, bool NTS>
+__global__ __launch_bounds__((zshape<N / 2, EMAX, THREADS>::NT)) void k_z_r2c_inplace(
+    const T* in, cx<T>* out, const cx<T>* __restrict__ tw,
+    int64_t rows, row_map map, T mul_edge, T mul_int) {
+    z_r2c_body<T, N, EMAX, THREADS, REMAP, NTS, true>(in, out, tw, rows, map, mul_edge, mul_int);
 }
 
 // ---------------------------------------------------------------- z C2R
-template <typename T, int N, int EMAX = 16, int THREADS = kThreads, bool REMAP = false,
-          bool NTS = false>
-__global__ __launch_bounds__((zshape<N / 2, EMAX, THREADS>::NT)) void k_z_c2r(
+template <typename T, int N, int EMAX, int THREADS, bool REMAP, bool NTS>
+__device__ __forceinline__ void z_c2r_body(
     const cx<T>* in, T* out, const cx<T>* __restrict__ tw,
     int64_t rows, row_map map, T mul_edge, T mul_int) {
     constexpr int M = N / 2, K = M + 1;
@@ -186,6 +214,22 @@ __global__ __launch_bounds__((zshape<N / 2, EMAX, THREADS>::NT)) void k_z_c2r(
             dst[t + m * TPT] = a[m];
         }
     }
+}
+
+template <typename T, int N, int EMAX, int THREADS, bool REMAP, bool NTS>
+__global__ __launch_bounds__((zshape<N / 2, EMAX, THREADS>::NT)) void k_z_c2r(
+    const cx<T>* __restrict__ in, T* __restrict__ out, const cx<T>* __restrict__ tw,
+    int64_t rows, row_map map, T mul_edge, T mul_int) {
+    z_c2r_body<T, N, EMAX, THREADS, REMAP, NTS>(in, out, tw, rows, map, mul_edge, mul_int);
+}
+
+// In place: every load of a row precedes the barrier after the LDS fill, and
+// every store follows the last barrier of the FFT.
+template <typename T, int N, int EMAX, int THREADS, bool REMAP, bool NTS>
+__global__ __launch_bounds__((zshape<N / 2, EMAX, THREADS>::NT)) void k_z_c2r_inplace(
+    const cx<T>* in, T* out, const cx<T>* __restrict__ tw,
+    int64_t rows, row_map map, T mul_edge, T mul_int) {
+    z_c2r_body<T, N, EMAX, THREADS, REMAP, NTS>(in, out, tw, rows, map, mul_edge, mul_int);
 }
 
 // ---------------------------------------------------------------- y / x C2C
@@ -380,9 +424,15 @@ static hipError_t z_r2c_n(const void* in, void* out, const void* tw, int64_t row
     const int64_t blocks = (rows + Z::RPB - 1) / Z::RPB;
     if (blocks == 0) return hipSuccess;
     if (blocks > kMaxBlocks) return hipErrorInvalidValue;
-    hipLaunchKernelGGL((k_z_r2c<T, N, C::EMAX, C::THREADS, C::REMAP, C::NTS>), dim3(blocks), dim3(Z::NT), 0, s,
-                       static_cast<const T*>(in), static_cast<cx<T>*>(out),
-                       static_cast<const cx<T>*>(tw), rows, map, T(me), T(mi));
+    if (in == out)
+        hipLaunchKernelGGL((k_z_r2c_inplace<T, N, C::EMAX, C::THREADS, C::REMAP, C::NTS>),
+                           dim3(blocks), dim3(Z::NT), 0, s, static_cast<const T*>(in),
+                           static_cast<cx<T>*>(out), static_cast<const cx<T>*>(tw), rows, map,
+                           T(me), T(mi));
+    else
+        hipLaunchKernelGGL((k_z_r2c<T, N, C::EMAX, C::THREADS, C::REMAP, C::NTS>), dim3(blocks),
+                           dim3(Z::NT), 0, s, static_cast<const T*>(in), static_cast<cx<T>*>(out),
+                           static_cast<const cx<T>*>(tw), rows, map, T(me), T(mi));
     return hipGetLastError();
 }
 
@@ -394,9 +444,15 @@ static hipError_t z_c2r_n(const void* in, void* out, const void* tw, int64_t row
     const int64_t blocks = (rows + Z::RPB - 1) / Z::RPB;
     if (blocks == 0) return hipSuccess;
     if (blocks > kMaxBlocks) return hipErrorInvalidValue;
-    hipLaunchKernelGGL((k_z_c2r<T, N, C::EMAX, C::THREADS, C::REMAP, C::NTS>), dim3(blocks), dim3(Z::NT), 0, s,
-                       static_cast<const cx<T>*>(in), static_cast<T*>(out),
-                       static_cast<const cx<T>*>(tw), rows, map, T(me), T(mi));
+    if (in == out)
+        hipLaunchKernelGGL((k_z_c2r_inplace<T, N, C::EMAX, C::THREADS, C::REMAP, C::NTS>),
+                           dim3(blocks), dim3(Z::NT), 0, s, static_cast<const cx<T>*>(in),
+                           static_cast<T*>(out), static_cast<const cx<T>*>(tw), rows, map,
+                           T(me), T(mi));
+    else
+        hipLaunchKernelGGL((k_z_c2r<T, N, C::EMAX, C::THREADS, C::REMAP, C::NTS>), dim3(blocks),
+                           dim3(Z::NT), 0, s, static_cast<const cx<T>*>(in), static_cast<T*>(out),
+                           static_cast<const cx<T>*>(tw), rows, map, T(me), T(mi));
     return hipGetLastError();
 }
 

@@ -68,3 +68,36 @@ def test_autograd_energy_loss_gradient():
         L.backward()
         ref = oracle.energy_loss_grad(uref[0])
         assert rel_l2(host(u.grad)[0], ref) <= TOL[dtype]
+
+
+def test_fp64_central_differences_energy_and_poisson():
+    """Both c5 losses through the FP64 autograd path: central differences
+    (eps = 1e-3, exact for a quadratic loss up to rounding) along seeded
+    uniform directions agree with the hand-written adjoint to 1e-8."""
+    import synth
+    n = 32
+    p = Plan(n, torch.float64)
+    k2 = torch.from_numpy(oracle.k_squared(n)).cuda()
+    w = torch.from_numpy(oracle.half_weights(n)).cuda()
+    m = torch.where(k2 > 0, -1.0 / torch.where(k2 > 0, k2, torch.ones_like(k2)),
+                    torch.zeros_like(k2))
+
+    def energy(u):
+        F = rfft3(u, p)
+        return torch.sum(w * k2 * (F.real ** 2 + F.imag ** 2))
+
+    def poisson_loss(f):
+        u = irfft3(m * rfft3(f, p), p, 1.0 / n ** 3)
+        return torch.sum(u ** 2)
+
+    for L, seed in ((energy, 230), (poisson_loss, 240)):
+        u0, _ = real_input(p.real_shape, seed, torch.float64)
+        u = u0.clone().requires_grad_(True)
+        L(u).backward()
+        eps = 1e-3
+        with torch.no_grad():
+            for s in range(3):
+                d = synth.uniform(p.real_shape, seed + 1 + s, torch.float64, "cuda")
+                fd = (L(u + eps * d).item() - L(u - eps * d).item()) / (2 * eps)
+                an = torch.sum(u.grad * d).item()
+                assert abs(fd - an) <= 1e-8 * max(1.0, abs(an)), (L.__name__, fd, an)

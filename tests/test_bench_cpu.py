@@ -1,0 +1,34 @@
+"""bench.py host logic without a GPU: refusal of several GPUs, the FLOP
+convention, and the recorded-traffic lookup (valid only for the kernel
+sources it was measured on)."""
+import os
+import subprocess
+import sys
+
+import bench
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def test_several_gpus_are_refused():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr
+
+
+def test_flop_convention():
+    # 5 (N^3/2) log2 N^3 per R2C, two per pair: 161.06 GFLOP at 1024^3
+    assert abs(bench.gflop_pair(1024) - 161.061273600) < 1e-6
+
+
+def test_recorded_traffic_requires_matching_sources(tmp_path):
+    got = bench.recorded_traffic(bench.TRAFFIC_FILE, "x_fwd")
+    if got is not None:                       # summary taken on these sources
+        assert 0.9 < got / (2 * 1024 * 1024 * 513 * 16) < 1.1
+    stale = tmp_path / "stale.md"
+    text = open(bench.TRAFFIC_FILE).read()
+    stale.write_text(text.replace(f"kernel_source_sha256_16: {bench.kernel_source_hash()}",
+                                  "kernel_source_sha256_16: 0000000000000000"))
+    assert bench.recorded_traffic(str(stale), "x_fwd") is None
+    assert bench.recorded_traffic(str(tmp_path / "missing.md"), "x_fwd") is None

@@ -86,10 +86,11 @@ __device__ __forceinline__ void z_r2c_body(
     const int64_t row = blk * RPB + rl;
     const bool valid = row < rows;
 
-    const cx<T>* src = reinterpret_cast<const cx<T>*>(in + row * map.rs);
+    // Rows past the end (last workgroup) load the last row and discard it.
+    const cx<T>* src = reinterpret_cast<const cx<T>*>(in + (valid ? row : rows - 1) * map.rs);
     cx<T> a[E];
 #pragma unroll
-    for (int m = 0; m < E; ++m) a[m] = valid ? src[t + m * TPT] : cx<T>{T(0), T(0)};
+    for (int m = 0; m < E; ++m) a[m] = src[t + m * TPT];
 
     const idx_rows<PS> ix{rl * MP};
     fft_regs<T, M, E, -1>(a, t, tw, 2, xch_full<T, idx_rows<PS>>{lds, ix});
@@ -169,17 +170,12 @@ __device__ __forceinline__ void z_c2r_body(
     // Load G[0..M-1] (registers and LDS) and G[M] (thread t = 0), dropping
     // the imaginary parts of kz = 0 and kz = N/2 and applying the bin
     // multipliers (scale, and 1/w for the adjoint).
+    // Rows past the end (last workgroup) load the last row and discard it.
     cx<T> g[E];
-    cx<T> g_m{T(0), T(0)};
-    if (valid) {
-        const cx<T>* src = in + map_row(row, map) * K;
+    const cx<T>* src = in + map_row(valid ? row : rows - 1, map) * K;
 #pragma unroll
-        for (int m = 0; m < E; ++m) g[m] = src[t + m * TPT];
-        if (t == 0) g_m = src[M];
-    } else {
-#pragma unroll
-        for (int m = 0; m < E; ++m) g[m] = cx<T>{T(0), T(0)};
-    }
+    for (int m = 0; m < E; ++m) g[m] = src[t + m * TPT];
+    cx<T> g_m = t == 0 ? src[M] : cx<T>{T(0), T(0)};
 #pragma unroll
     for (int m = 0; m < E; ++m) {
         const int k = t + m * TPT;

@@ -21,6 +21,22 @@ namespace gfft {
 
 constexpr int kThreads = 256;
 
+constexpr int ilog2_c(int v) { return v <= 1 ? 0 : 1 + ilog2_c(v / 2); }
+
+// A workgroup-uniform value in scalar registers that the optimiser cannot
+// see through: expressions of it are formed where they are used.
+__device__ __forceinline__ int opaque_uniform(int v) {
+    int r = __builtin_amdgcn_readfirstlane(v);
+    asm volatile("" : "+s"(r));
+    return r;
+}
+__device__ __forceinline__ int64_t opaque_uniform(int64_t v) {
+    const uint64_t u = uint64_t(v);
+    const uint32_t lo = uint32_t(opaque_uniform(int(uint32_t(u)))),
+                   hi = uint32_t(opaque_uniform(int(uint32_t(u >> 32))));
+    return int64_t((uint64_t(hi) << 32) | lo);
+}
+
 __device__ __forceinline__ int64_t map_row(int64_t r, row_map m) {
     const int64_t bx = r >> m.lg_n;
     const int64_t y = r & ((int64_t(1) << m.lg_n) - 1);
@@ -280,16 +296,32 @@ __global__ __launch_bounds__(TC * N / E) void k_strided(
     const bool valid = m < m_cols;
     const int64_t ymask = (int64_t(1) << lm.lg_y) - 1;
     cx<T>* plane = data + (b >> lm.lg_bx) * lm.b_hi + (b & ((int64_t(1) << lm.lg_bx) - 1)) * lm.b_lo;
-    cx<T>* base = plane + m;
     auto off = [&](int64_t n) { return (n >> lm.lg_y) * lm.s_hi + (n & ymask) * lm.s_lo; };
+    // Element n = t + i*TPT of a line: t < TPT and i*TPT have disjoint bits
+    // (TPT a power of two), and off() adds over disjoint bit fields, so
+    // off(n) = off(t) + off(i*TPT): a per-lane pointer plus an offset that
+    // is the same for the whole workgroup, written in closed form as
+    // off(i*TPT) = (i >> d) H + (i mod 2^d) Lo.  Lanes of the ragged last
+    // tile read the last column instead (in bounds); their results are
+    // dropped.
+    constexpr int LGT = ilog2_c(TPT), LGE = ilog2_c(E);
+    int d = 0;
+    int64_t H = (int64_t(TPT) >> (lm.lg_y < LGT ? lm.lg_y : LGT)) * lm.s_hi, Lo = 0;
+    if (lm.lg_y >= LGT) {
+        d = lm.lg_y - LGT < LGE ? lm.lg_y - LGT : LGE;
+        H = lm.s_hi;
+        Lo = int64_t(TPT) * lm.s_lo;
+    }
+    auto uoff = [](int i, int d, int64_t H, int64_t Lo) {
+        return int64_t(i >> d) * H + int64_t(i & ((1 << d) - 1)) * Lo;
+    };
+    int64_t lane_off = (valid ? m : m_cols - 1) + off(t);
+    const cx<T>* lane = plane + lane_off;
 
     cx<T> a[E];
     if constexpr (MF == 0) {
 #pragma unroll
-        for (int i = 0; i < E; ++i) {
-            const int64_t n = t + i * TPT;
-            a[i] = valid ? base[off(n)] : cx<T>{T(0), T(0)};
-        }
+        for (int i = 0; i < E; ++i) a[i] = lane[uoff(i, d, H, Lo)];
         if constexpr (XP > 2)
             fft_regs<T, N, E, S>(a, t, tw, 1,
                                  xch_parts<T, IX, XP / 2>{reinterpret_cast<T*>(lds), IX{c}});
@@ -362,11 +394,15 @@ __global__ __launch_bounds__(TC * N / E) void k_strided(
             fft_from<T, N, E, S, 16>(a, t, tw, 1, xch_full<T, IX>{lds, IX{c}});
     }
     if (!valid) return;
+    // Opaque to the optimiser, so the store addresses are formed afresh
+    // instead of keeping the E load addresses live through the transform.
+    asm volatile("" : "+v"(lane_off));
+    d = opaque_uniform(d);
+    H = opaque_uniform(H);
+    Lo = opaque_uniform(Lo);
+    cx<T>* dst = plane + lane_off;
 #pragma unroll
-    for (int i = 0; i < E; ++i) {
-        const int64_t n = t + i * TPT;
-        base[off(n)] = a[i];
-    }
+    for (int i = 0; i < E; ++i) dst[uoff(i, d, H, Lo)] = a[i];
 }
 
 // ---------------------------------------------------------------- pack

@@ -66,19 +66,21 @@ struct zshape {
     static constexpr int RPB = NT / TPT;           // rows per workgroup
 };
 
-// Workgroup shape of the z passes, chosen by measurement at 1024^3 and
-// 4096^2 rows: FP64 R2C 8 elements per thread (16 for N >= 2048) in
-// 256-thread workgroups, FP64 C2R 16 per thread in 64-thread workgroups,
-// FP32 32 per thread in 64-thread ones.
-// The C2R deals its workgroups to XCDs in contiguous ranges and stores its
-// aligned real rows non-temporally (they are not read again soon): 3-5%
-// faster in FP64.  The R2C, whose complex rows are not line-aligned, gains
-// from neither (the XCD order cost FP32 15%), so it keeps the plain order.
+// Workgroup shape of the z passes, chosen by measurement (2^18 and 2^20
+// rows): FP64 R2C 8 elements per thread in 256-thread workgroups up to
+// N = 512, 16 per thread in 128-thread ones for N = 1024 and 2048 (7-8%
+// faster there), 32 per thread for N = 4096; FP64 C2R 16 per thread in
+// 64-thread workgroups; FP32 32 per thread in 64-thread ones.
+// From N = 1024 up, workgroups are dealt to XCDs in contiguous ranges
+// (2-3% on the R2C, 3-5% on the C2R).  The C2R also stores its line-aligned
+// real rows non-temporally (they are not read again soon); the R2C's
+// complex rows are not line-aligned and gain nothing from it.
 template <typename T, bool FWD, int N>
 struct zcfg {
-    static constexpr int EMAX = sizeof(T) == 8 ? (FWD ? (N >= 2048 ? 16 : 8) : 16) : 32;
-    static constexpr int THREADS = sizeof(T) == 8 && FWD ? 256 : 64;
-    static constexpr bool REMAP = !FWD;
+    static constexpr bool F64 = sizeof(T) == 8;
+    static constexpr int EMAX = F64 ? (FWD ? (N >= 4096 ? 32 : N >= 1024 ? 16 : 8) : 16) : 32;
+    static constexpr int THREADS = F64 && FWD ? (N >= 1024 ? 128 : 256) : 64;
+    static constexpr bool REMAP = !FWD || N >= 1024;
     static constexpr bool NTS = !FWD;
 };
 

@@ -49,8 +49,11 @@ def test_fused_pack_forward_and_inverse(n, p, dtype):
 
 
 @pytest.mark.parametrize("dtype", [torch.float64, torch.float32], ids=["f64", "f32"])
-@pytest.mark.parametrize("n,p", [(32, 2), (64, 4), (64, 8)])
+@pytest.mark.parametrize("n,p", [(32, 2), (64, 4), (64, 8), (256, 32)])
 def test_virtual_ranks_match_full_grid(n, p, dtype):
+    """(256, 32): chunks of N/p = 8 rows, fewer than the 16 threads that
+    share a line, so each line element's offset splits between both levels
+    of the send-order layout."""
     x = n // p
     k = n // 2 + 1
     f, fref = real_input((n, n, n), 300 + n + p, dtype)
@@ -126,7 +129,7 @@ def test_paper_order_pack_bit_exact(n, p, dtype):
 
 
 @pytest.mark.parametrize("dtype", [torch.float64, torch.float32], ids=["f64", "f32"])
-@pytest.mark.parametrize("n,p", [(32, 2), (64, 4), (64, 8)])
+@pytest.mark.parametrize("n,p", [(32, 2), (64, 4), (64, 8), (256, 32)])
 def test_paper_order_virtual_ranks(n, p, dtype):
     """Steps 1-5 with the paper's wire format: the local xy transpose folded
     into the z pass, chunk transposes folded into the x pass."""

@@ -277,7 +277,9 @@ struct sshape {
 // XP: LDS rounds per exchange.  1 = whole complex values, 2 = real then
 // imaginary parts, 2P (P > 1) = real and imaginary parts of P position
 // ranges; the LDS tile is N*TC/XP complex values.
-template <typename T, int N, int TC, int XP, int S, int E = 16, int MF = 0>
+// NT: non-temporal loads and stores of the lines (no reuse), for tilings in
+// which every 128-byte line belongs to one tile (the host checks this).
+template <typename T, int N, int TC, int XP, int S, int E = 16, int MF = 0, bool NT = false>
 __global__ __launch_bounds__(TC * N / E) void k_strided(
     cx<T>* __restrict__ data, const cx<T>* __restrict__ tw, int64_t m_cols,
     int64_t tiles_m, line_map lm) {
@@ -323,7 +325,15 @@ __global__ __launch_bounds__(TC * N / E) void k_strided(
     cx<T> a[E];
     if constexpr (MF == 0) {
 #pragma unroll
-        for (int i = 0; i < E; ++i) a[i] = lane[uoff(i, d, H, Lo)];
+        for (int i = 0; i < E; ++i) {
+            const cx<T>* p = lane + uoff(i, d, H, Lo);
+            if constexpr (NT) {
+                a[i].x = __builtin_nontemporal_load(&p->x);
+                a[i].y = __builtin_nontemporal_load(&p->y);
+            } else {
+                a[i] = *p;
+            }
+        }
         if constexpr (XP > 2)
             fft_regs<T, N, E, S>(a, t, tw, 1,
                                  xch_parts<T, IX, XP / 2>{reinterpret_cast<T*>(lds), IX{c}});
@@ -404,7 +414,15 @@ __global__ __launch_bounds__(TC * N / E) void k_strided(
     Lo = opaque_uniform(Lo);
     cx<T>* dst = plane + lane_off;
 #pragma unroll
-    for (int i = 0; i < E; ++i) dst[uoff(i, d, H, Lo)] = a[i];
+    for (int i = 0; i < E; ++i) {
+        cx<T>* p = dst + uoff(i, d, H, Lo);
+        if constexpr (NT) {
+            __builtin_nontemporal_store(a[i].x, &p->x);
+            __builtin_nontemporal_store(a[i].y, &p->y);
+        } else {
+            *p = a[i];
+        }
+    }
 }
 
 // ---------------------------------------------------------------- pack
@@ -490,6 +508,14 @@ static hipError_t z_c2r_n(const void* in, void* out, const void* tw, int64_t row
     return hipGetLastError();
 }
 
+// True when each tile of a multiple of `la` columns covers whole lines of
+// `la` elements: the base is 128-byte aligned and every offset of the
+// layout, and the column count, are multiples of `la`.
+static bool whole_lines(const void* data, int64_t m_cols, const line_map& lm, int64_t la) {
+    return reinterpret_cast<uintptr_t>(data) % 128 == 0 && m_cols % la == 0 &&
+           lm.b_hi % la == 0 && lm.b_lo % la == 0 && lm.s_hi % la == 0 && lm.s_lo % la == 0;
+}
+
 template <typename T, int N, int AX, int MF>
 static hipError_t strided_ax(int sign, void* data, const void* tw, int64_t m_cols,
                              int64_t n_b, line_map lm, hipStream_t s) {
@@ -500,6 +526,23 @@ static hipError_t strided_ax(int sign, void* data, const void* tw, int64_t m_col
     if (blocks == 0) return hipSuccess;
     if (blocks > kMaxBlocks) return hipErrorInvalidValue;
     const dim3 threads(TC * SH::TPT);
+    // x lines of large grids stream through non-temporally when every tile
+    // owns whole 128-byte lines: 2% faster in FP64, 4% in FP32 at 1024^3.
+    // (Where neighbouring tiles share lines, as in the y passes, the hint
+    // makes the shared lines travel twice and costs 15-30%.)
+    if constexpr (AX == 1 && MF == 0 && N >= 512 && (TC * sizeof(cx<T>)) % 128 == 0) {
+        if (whole_lines(data, m_cols, lm, 128 / int64_t(sizeof(cx<T>)))) {
+            if (sign < 0)
+                hipLaunchKernelGGL((k_strided<T, N, TC, SH::XP, -1, SH::E, 0, true>), dim3(blocks),
+                                   threads, 0, s, static_cast<cx<T>*>(data),
+                                   static_cast<const cx<T>*>(tw), m_cols, tiles_m, lm);
+            else
+                hipLaunchKernelGGL((k_strided<T, N, TC, SH::XP, +1, SH::E, 0, true>), dim3(blocks),
+                                   threads, 0, s, static_cast<cx<T>*>(data),
+                                   static_cast<const cx<T>*>(tw), m_cols, tiles_m, lm);
+            return hipGetLastError();
+        }
+    }
     if (sign < 0)
         hipLaunchKernelGGL((k_strided<T, N, TC, SH::XP, -1, SH::E, MF>), dim3(blocks), threads,
                            0, s, static_cast<cx<T>*>(data), static_cast<const cx<T>*>(tw),

@@ -98,6 +98,18 @@ typedef struct {
     int64_t complex_bytes; /* batch * X * N * K complex (= send buffer)    */
     int64_t pencil_bytes;  /* batch * N * (N/p) * K complex, x-pencil      */
     int64_t chunk_bytes;   /* one all-to-all chunk: X * (N/p) * K complex  */
+    /* Pencil plans (gfft_pencil_plan_create) reuse the fields above as:
+     * slab_x = X = N/pr, ranks = pr * pc, real_bytes = batch * X * Y * N
+     * reals, complex_bytes = batch * X * Y * K complex (first-exchange
+     * order), pencil_bytes = batch * pc * X * Y * w complex (the y- and
+     * x-pencils), chunk_bytes = X * Y * w complex (one block of either
+     * exchange per source rank, per grid).  Slab plans report grid_r = p,
+     * grid_c = 1, col = 0, y_local = N, kz_width = K. */
+    int64_t grid_r;        /* pr: process-grid rows (x is cut pr ways)     */
+    int64_t grid_c;        /* pc: process-grid columns (y, then kz)        */
+    int64_t col;           /* this rank's column c, 0 <= c < pc            */
+    int64_t y_local;       /* Y = N/pc local y extent of the real pencil   */
+    int64_t kz_width;      /* w: kz bins this rank holds after exchange 1  */
 } gfft_plan_sizes;
 
 /*
@@ -119,6 +131,48 @@ typedef struct {
  */
 gfft_status gfft_plan_create(gfft_plan **out, int64_t n, gfft_dtype dtype,
                              int64_t slab_x, int64_t batch, uint32_t flags);
+
+/*
+ * Create a plan for one GPU's share of a pencil-decomposed N^3 real grid
+ * (section 2, pencil decomposition: p = pr x pc processors, each holding
+ * (N/pr) x (N/pc) x N real values; up to N^2/4 processors here, so p may
+ * exceed N, the slab limit).  Rank (r, c) owns x in [r X, (r+1) X) and y in
+ * [c Y, (c+1) Y), X = N/pr, Y = N/pc, all z.  The forward transform is
+ *   1. gfft_exec_z_r2c: rows [batch][X][Y][N] -> half-spectrum rows written
+ *      straight in first-exchange order: chunk c' (for rank (r, c')) holds
+ *      kz in [c' w0, (c'+1) w0), w0 = N/(2 pc), and the last chunk also the
+ *      Nyquist bin kz = N/2; chunk c' is a [X][Y][w_c'] block and the chunks
+ *      lie back to back (X Y K complex per grid).
+ *   2. exchange 1 (caller, among the pc ranks of row r): rank (r, c)
+ *      receives chunk c of every (r, c') into block c' of its y-pencil
+ *      [pc][X][Y][w] (w = w_c): element (c', x_l, y_l, kz_l) is
+ *      (x = r X + x_l, y = c' Y + y_l, kz = c w0 + kz_l).
+ *   3. gfft_exec_y_c2c: in place along y on that y-pencil.
+ *   4. exchange 2 (caller, among the pr ranks of column c): with g = pc/pr,
+ *      blocks c' in [r' g, (r'+1) g) of the y-pencil -- one contiguous run
+ *      of g X Y w values -- go to rank (r', c), which stores the run from
+ *      rank (r, c) as block r of its x-pencil [pr][g][X][Y][w]: element
+ *      (r, g_l, x_l, y_l, kz_l) is (x = r X + x_l, y = r' N/pr + g_l Y +
+ *      y_l, kz = c w0 + kz_l).
+ *   5. gfft_exec_x_c2c: in place along x on that x-pencil.
+ * The inverse runs 5, 4, 3, 2, 1 backwards (gfft_exec_x_c2c and
+ * gfft_exec_y_c2c with sign +1, the exchanges returning every block to its
+ * sender, gfft_exec_z_c2r reading the first-exchange order).  Each exchange
+ * is per grid of the batch.
+ *   grid_r, grid_c : pr, pc, powers of two with pr <= pc <= N/2.
+ *   col            : this rank's c (it fixes w: w0, or w0 + 1 when
+ *                    c = pc - 1).
+ *   flags          : 0 or one of GFFT_MFMA_BF16X2 / GFFT_MFMA_BF16X3 (FP32,
+ *                    N >= 32); the slab flags return GFFT_E_UNSUPPORTED.
+ * gfft_exec_r2c / c2r / the adjoints and the slab pack/unpack return
+ * GFFT_E_UNSUPPORTED on pencil plans (their local work is steps 1 and 5
+ * apart); gfft_exec_z_r2c's scale/weighted arguments give the adjoint's
+ * bin factors as for slabs.
+ */
+gfft_status gfft_pencil_plan_create(gfft_plan **out, int64_t n,
+                                    gfft_dtype dtype, int64_t grid_r,
+                                    int64_t grid_c, int64_t col,
+                                    int64_t batch, uint32_t flags);
 
 /* Free a plan and its tables (NULL is accepted).  The caller must ensure no
  * work using the plan is still queued. */

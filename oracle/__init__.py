@@ -18,7 +18,10 @@ Transform on GPUs"):
   * section 2, slab decomposition: rank r owns x in [r N/p, (r+1) N/p);
   * section 3, steps 1-5 of the forward algorithm: 2D R2C on every yz plane,
     local xy transpose, all-to-all in chunks of (N/p) x (N/p) x K, chunk
-    transpose, strided 1D C2C along x; the inverse runs them in reverse order.
+    transpose, strided 1D C2C along x; the inverse runs them in reverse order;
+  * section 2, pencil decomposition: a pr x pc grid of ranks holding
+    (N/pr) x (N/pc) x N real values each (the spectral layouts of the two
+    exchanges are the library's reading, written out below).
 
 Every function here is unnormalized; ``scale`` arguments multiply results.
 """
@@ -228,6 +231,112 @@ def exchange(sends: list[np.ndarray]) -> list[np.ndarray]:
 def x_c2c(pencil: np.ndarray, sign: int, method=None) -> np.ndarray:
     """Step 5: strided batched 1D DFT along x of an [..., N, Y, K] pencil."""
     return c2c_axis(pencil, -3, sign, method)
+
+
+# --------------------------------------------------------------------------
+# Pencil decomposition (section 2): p = pr x pc ranks, rank (r, c) holding
+# the (N/pr) x (N/pc) x N real values x in [r X, (r+1) X), y in [c Y,
+# (c+1) Y).  The paper names this decomposition but fixes none of its
+# spectral layouts; the ones written out here are the library's reading
+# (pr <= pc <= N/2): two exchanges, kz cut across the grid columns.
+# --------------------------------------------------------------------------
+
+def pencil_kz_range(n: int, pc: int, c: int) -> tuple[int, int]:
+    """Bins [k0, k1) of kz that grid column c holds after exchange 1: N/(2 pc)
+    bins each, and the Nyquist bin kz = N/2 with the last column."""
+    w0 = n // (2 * pc)
+    return c * w0, (c + 1) * w0 + (1 if c == pc - 1 else 0)
+
+
+def pencil_send(rows: np.ndarray, pc: int) -> np.ndarray:
+    """First-exchange order of a rank's half-spectrum rows [..., X, Y, K]:
+    chunk c' (for rank (r, c')) is its kz bins as an [X][Y][w_c'] block;
+    the chunks lie back to back -> [..., X*Y*K]."""
+    *lead, x, y, k = rows.shape
+    n = 2 * (k - 1)
+    parts = []
+    for c in range(pc):
+        k0, k1 = pencil_kz_range(n, pc, c)
+        parts.append(rows[..., k0:k1].reshape(*lead, x * y * (k1 - k0)))
+    return np.concatenate(parts, axis=-1)
+
+
+def pencil_unsend(flat: np.ndarray, x: int, y: int, pc: int) -> np.ndarray:
+    """Inverse of :func:`pencil_send`: [..., X*Y*K] -> [..., X, Y, K]."""
+    *lead, total = flat.shape
+    k = total // (x * y)
+    n = 2 * (k - 1)
+    out = np.empty((*lead, x, y, k), dtype=flat.dtype)
+    for c in range(pc):
+        k0, k1 = pencil_kz_range(n, pc, c)
+        out[..., k0:k1] = flat[..., x * y * k0:x * y * k1].reshape(*lead, x, y, k1 - k0)
+    return out
+
+
+def pencil_exchange1(sends: list[np.ndarray], x: int, y: int) -> list[np.ndarray]:
+    """Exchange 1 inside one grid row: ``sends[c']`` is rank (r, c')'s
+    first-exchange buffer [..., X*Y*K]; rank (r, c) receives chunk c of every
+    rank into block c' of its y-pencil [..., pc, X, Y, w_c]."""
+    pc = len(sends)
+    k = sends[0].shape[-1] // (x * y)
+    n = 2 * (k - 1)
+    out = []
+    for c in range(pc):
+        k0, k1 = pencil_kz_range(n, pc, c)
+        blocks = [s[..., x * y * k0:x * y * k1].reshape(*s.shape[:-1], x, y, k1 - k0)
+                  for s in sends]
+        out.append(np.stack(blocks, axis=-4))
+    return out
+
+
+def pencil_exchange1_back(ypencils: list[np.ndarray]) -> list[np.ndarray]:
+    """Inverse of :func:`pencil_exchange1`: every block back to its sender,
+    giving each rank (r, c') its first-exchange buffer [..., X*Y*K]."""
+    pc = len(ypencils)
+    lead = ypencils[0].shape[:-4]
+    out = []
+    for cp in range(pc):
+        out.append(np.concatenate([ypencils[c][..., cp, :, :, :].reshape(*lead, -1)
+                                   for c in range(pc)], axis=-1))
+    return out
+
+
+def pencil_y_c2c(ypencil: np.ndarray, sign: int, method=None) -> np.ndarray:
+    """1D DFT along y of a y-pencil [..., pc, X, Y, w] (y = c' Y + y_l)."""
+    *lead, pc, x, y, w = ypencil.shape
+    nl = len(lead)
+    perm = list(range(nl)) + [nl + 1, nl, nl + 2, nl + 3]        # -> [X, pc, Y, w]
+    lines = np.ascontiguousarray(ypencil.transpose(perm)).reshape(*lead, x, pc * y, w)
+    lines = c2c_axis(lines, -2, sign, method)
+    return np.ascontiguousarray(lines.reshape(*lead, x, pc, y, w).transpose(perm))
+
+
+def pencil_exchange2(ypencils: list[np.ndarray], pr: int) -> list[np.ndarray]:
+    """Exchange 2 inside one grid column: ``ypencils[r]`` is rank (r, c)'s
+    y-pencil [..., pc, X, Y, w]; rank (r', c) receives blocks [r' g,
+    (r'+1) g) (g = pc/pr) of every rank r as block r of its x-pencil
+    [..., pr, g, X, Y, w]."""
+    pc = ypencils[0].shape[-4]
+    g = pc // pr
+    return [np.stack([yp[..., rp * g:(rp + 1) * g, :, :, :] for yp in ypencils], axis=-5)
+            for rp in range(pr)]
+
+
+def pencil_exchange2_back(xpencils: list[np.ndarray]) -> list[np.ndarray]:
+    """Inverse of :func:`pencil_exchange2`."""
+    pr = len(xpencils)
+    return [np.concatenate([xpencils[rp][..., r, :, :, :, :] for rp in range(pr)], axis=-4)
+            for r in range(pr)]
+
+
+def pencil_x_c2c(xpencil: np.ndarray, sign: int, method=None) -> np.ndarray:
+    """1D DFT along x of an x-pencil [..., pr, g, X, Y, w] (x = r X + x_l)."""
+    *lead, pr, g, x, y, w = xpencil.shape
+    nl = len(lead)
+    perm = list(range(nl)) + [nl + 1, nl, nl + 2, nl + 3, nl + 4]  # -> [g, pr, X, Y, w]
+    lines = np.ascontiguousarray(xpencil.transpose(perm)).reshape(*lead, g, pr * x, y, w)
+    lines = c2c_axis(lines, -3, sign, method)
+    return np.ascontiguousarray(lines.reshape(*lead, g, pr, x, y, w).transpose(perm))
 
 
 # --------------------------------------------------------------------------

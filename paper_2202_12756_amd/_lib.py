@@ -31,7 +31,7 @@ GFFT_PACK_PAPER_ORDER = 1 << 4
 
 # Every symbol include/gfft.h declares.
 EXPORTS = (
-    "gfft_plan_create", "gfft_plan_destroy", "gfft_plan_query",
+    "gfft_plan_create", "gfft_pencil_plan_create", "gfft_plan_destroy", "gfft_plan_query",
     "gfft_exec_r2c", "gfft_exec_c2r", "gfft_exec_r2c_adjoint",
     "gfft_exec_c2r_adjoint", "gfft_pack_slab_for_alltoall",
     "gfft_unpack_slab_from_alltoall", "gfft_exec_x_c2c",
@@ -43,7 +43,7 @@ EXPORTS = (
 class gfft_plan_sizes(ctypes.Structure):
     _fields_ = [(name, ctypes.c_int64) for name in (
         "n", "slab_x", "ranks", "batch", "k", "real_bytes", "complex_bytes",
-        "pencil_bytes", "chunk_bytes")]
+        "pencil_bytes", "chunk_bytes", "grid_r", "grid_c", "col", "y_local", "kz_width")]
 
 
 class GfftError(RuntimeError):
@@ -68,6 +68,7 @@ def load(path: str = LIB_PATH):
                               ctypes.c_uint32, ctypes.c_double)
     sig = {
         "gfft_plan_create": [ctypes.POINTER(vp), i64, i32, i64, i64, u32],
+        "gfft_pencil_plan_create": [ctypes.POINTER(vp), i64, i32, i64, i64, i64, i64, u32],
         "gfft_plan_destroy": [vp],
         "gfft_plan_query": [vp, ctypes.POINTER(gfft_plan_sizes)],
         "gfft_exec_r2c": [vp, vp, vp, vp],
@@ -106,6 +107,13 @@ def check(status: int, where: str) -> None:
 def gfft_plan_create(n, dtype, slab_x, batch, flags):
     h = ctypes.c_void_p()
     st = load().gfft_plan_create(ctypes.byref(h), n, dtype, slab_x, batch, flags)
+    return st, h
+
+
+def gfft_pencil_plan_create(n, dtype, grid_r, grid_c, col, batch, flags):
+    h = ctypes.c_void_p()
+    st = load().gfft_pencil_plan_create(ctypes.byref(h), n, dtype, grid_r, grid_c, col, batch,
+                                        flags)
     return st, h
 
 

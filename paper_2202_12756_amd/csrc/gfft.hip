@@ -19,6 +19,13 @@ struct gfft_plan {
     uint32_t flags;
     int device;
     void* tw;  // W_N^m, m = 0..N-1, in the working precision
+    // z rows per grid: X * N (slab), X * Y (pencil: x and y extents local)
+    int64_t zrows;
+    // pencil plans: pr x pc process grid, this rank's column `col`, its kz
+    // width w = N/(2 pc) (+1 for the last column), g = pc / pr
+    bool pencil;
+    int64_t pr, pc, col, w, g;
+    int lg_w0, lg_g;
 };
 
 namespace {
@@ -75,8 +82,8 @@ bool overlap(const void* a, int64_t na, const void* b, int64_t nb) {
     return x < y + uint64_t(nb) && y < x + uint64_t(na);
 }
 
-int64_t real_size(const gfft_plan* p) { return p->batch * p->x * p->n * p->rs; }
-int64_t cplx_count(const gfft_plan* p) { return p->batch * p->x * p->n * p->k; }
+int64_t real_size(const gfft_plan* p) { return p->batch * p->zrows * p->rs; }
+int64_t cplx_count(const gfft_plan* p) { return p->batch * p->zrows * p->k; }
 int64_t elt(const gfft_plan* p) { return p->dtype == GFFT_F64 ? 8 : 4; }
 int64_t real_bytes(const gfft_plan* p) { return real_size(p) * elt(p); }
 int64_t cplx_bytes(const gfft_plan* p) { return cplx_count(p) * 2 * elt(p); }
@@ -86,6 +93,14 @@ bool paper(const gfft_plan* p) { return (p->flags & GFFT_PACK_PAPER_ORDER) != 0;
 // Rows of the half spectrum that the z passes write or read: natural, or one
 // of the two send orders when the pack is fused.
 gfft::row_map zmap(const gfft_plan* p) {
+    if (p->pencil) {
+        gfft::row_map m{p->lg_n, p->lg_x, p->lg_n, p->rs, 0};
+        m.pencil = 1;
+        m.lg_rows = p->lg_x + p->lg_y;
+        m.lg_w = p->lg_w0;
+        m.pc_last = int(p->pc - 1);
+        return m;
+    }
     const bool packed = (p->flags & GFFT_FUSE_PACK) != 0;
     return gfft::row_map{p->lg_n, p->lg_x, packed ? p->lg_y : p->lg_n, p->rs,
                          packed && paper(p) ? 1 : 0};
@@ -99,8 +114,17 @@ gfft::row_map packmap(const gfft_plan* p) {
 // y lines of a [batch][X][N][K] half spectrum: natural, send order
 // [p][X][N/p][K], or the paper's order [N][X][K] (slab transposed).
 gfft::line_map ymap(const gfft_plan* p) {
-    const bool packed = (p->flags & GFFT_FUSE_PACK) != 0;
     gfft::line_map lm;
+    if (p->pencil) {  // [batch][pc][X][Y][w]: y = c' Y + y_l, planes x_l
+        lm.b_hi = p->pc * p->x * p->y * p->w;
+        lm.lg_bx = p->lg_x;
+        lm.b_lo = p->y * p->w;
+        lm.s_hi = p->x * p->y * p->w;
+        lm.s_lo = p->w;
+        lm.lg_y = p->lg_y;
+        return lm;
+    }
+    const bool packed = (p->flags & GFFT_FUSE_PACK) != 0;
     lm.b_hi = p->x * p->n * p->k;
     lm.lg_bx = p->lg_x;
     if (packed && paper(p)) {
@@ -123,6 +147,15 @@ gfft::line_map ymap(const gfft_plan* p) {
 // step 4 folded into the addressing (a batch of Y line sets, K columns each).
 gfft::line_map xmap(const gfft_plan* p) {
     gfft::line_map lm;
+    if (p->pencil) {  // [batch][pr][g][X][Y][w]: x = r X + x_l, line sets (item, g_l)
+        lm.b_hi = p->pc * p->x * p->y * p->w;
+        lm.lg_bx = p->lg_g;
+        lm.b_lo = p->x * p->y * p->w;
+        lm.s_hi = p->g * p->x * p->y * p->w;
+        lm.s_lo = p->y * p->w;
+        lm.lg_y = p->lg_x;
+        return lm;
+    }
     if (paper(p)) {
         lm.b_hi = p->n * p->y * p->k;
         lm.b_lo = p->x * p->k;
@@ -151,14 +184,14 @@ gfft_status run_z_r2c(const gfft_plan* p, const void* in, void* out, double scal
                       bool weighted, hipStream_t s) {
     const double me = scale, mi = weighted ? 2.0 * scale : scale;
     return hip_status(gfft::launch_z_r2c(f64(p), int(p->n), in, out, p->tw,
-                                         p->batch * p->x * p->n, zmap(p), me, mi, s));
+                                         p->batch * p->zrows, zmap(p), me, mi, s));
 }
 
 gfft_status run_z_c2r(const gfft_plan* p, const void* in, void* out, double scale,
                       bool weighted, hipStream_t s) {
     const double me = scale, mi = weighted ? 0.5 * scale : scale;
     return hip_status(gfft::launch_z_c2r(f64(p), int(p->n), in, out, p->tw,
-                                         p->batch * p->x * p->n, zmap(p), me, mi, s));
+                                         p->batch * p->zrows, zmap(p), me, mi, s));
 }
 
 int mfma_terms(const gfft_plan* p) {
@@ -168,13 +201,14 @@ int mfma_terms(const gfft_plan* p) {
 }
 
 gfft_status run_y(const gfft_plan* p, void* data, int sign, hipStream_t s) {
+    const int64_t cols = p->pencil ? p->w : p->k;
     return hip_status(gfft::launch_strided(f64(p), int(p->n), 0, mfma_terms(p), sign, data,
-                                           p->tw, p->k, p->batch * p->x, ymap(p), s));
+                                           p->tw, cols, p->batch * p->x, ymap(p), s));
 }
 
 gfft_status run_x(const gfft_plan* p, void* data, int sign, hipStream_t s) {
-    const int64_t cols = paper(p) ? p->k : p->y * p->k;
-    const int64_t sets = paper(p) ? p->batch * p->y : p->batch;
+    const int64_t cols = p->pencil ? p->y * p->w : paper(p) ? p->k : p->y * p->k;
+    const int64_t sets = p->pencil ? p->batch * p->g : paper(p) ? p->batch * p->y : p->batch;
     return hip_status(gfft::launch_strided(f64(p), int(p->n), 1, mfma_terms(p), sign, data,
                                            p->tw, cols, sets, xmap(p), s));
 }
@@ -195,6 +229,7 @@ gfft_status forward(const gfft_plan* p, const void* in, void* out, double scale,
                     bool weighted, void* stream) {
     gfft_status st = check_r2c_args(p, in, out);
     if (st != GFFT_OK) return st;
+    if (p->pencil) return GFFT_E_UNSUPPORTED;
     if (!std::isfinite(scale)) return GFFT_E_INVALID_ARG;
     hipStream_t s = as_stream(stream);
     if ((st = run_z_r2c(p, in, out, scale, weighted, s)) != GFFT_OK) return st;
@@ -207,11 +242,54 @@ gfft_status inverse(const gfft_plan* p, void* in, void* out, double scale, bool 
                     void* stream) {
     gfft_status st = check_r2c_args(p, out, in);
     if (st != GFFT_OK) return st;
+    if (p->pencil) return GFFT_E_UNSUPPORTED;
     if (!std::isfinite(scale)) return GFFT_E_INVALID_ARG;
     hipStream_t s = as_stream(stream);
     if (p->p == 1 && (st = run_x(p, in, +1, s)) != GFFT_OK) return st;
     if ((st = run_y(p, in, +1, s)) != GFFT_OK) return st;
     return run_z_c2r(p, in, out, scale, weighted, s);
+}
+
+// The current device, if it is a gfx950.
+gfft_status usable_device(int* dev) {
+    int count = 0;
+    if (hipGetDeviceCount(&count) != hipSuccess || count < 1) return GFFT_E_NO_DEVICE;
+    if (hipGetDevice(dev) != hipSuccess) return GFFT_E_HIP;
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, *dev) != hipSuccess) return GFFT_E_HIP;
+    if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0) return GFFT_E_NO_DEVICE;
+    return GFFT_OK;
+}
+
+// FP64 twiddles W_N^m, m = 0..N-1, rounded once to the working precision,
+// into a device table owned by the plan.
+gfft_status upload_twiddles(gfft_plan* p) {
+    const int64_t n = p->n;
+    const size_t bytes = size_t(n) * 2 * (p->dtype == GFFT_F64 ? 8 : 4);
+    std::vector<unsigned char> host(bytes);
+    for (int64_t m = 0; m < n; ++m) {
+        double re, im;
+        unit_root(m, n, &re, &im);
+        if (p->dtype == GFFT_F64) {
+            double* h = reinterpret_cast<double*>(host.data());
+            h[2 * m] = re;
+            h[2 * m + 1] = im;
+        } else {
+            float* h = reinterpret_cast<float*>(host.data());
+            h[2 * m] = float(re);
+            h[2 * m + 1] = float(im);
+        }
+    }
+    if (hipMalloc(&p->tw, bytes) != hipSuccess) {
+        p->tw = nullptr;
+        return GFFT_E_NOMEM;
+    }
+    if (hipMemcpy(p->tw, host.data(), bytes, hipMemcpyHostToDevice) != hipSuccess) {
+        (void)hipFree(p->tw);
+        p->tw = nullptr;
+        return GFFT_E_HIP;
+    }
+    return GFFT_OK;
 }
 
 }  // namespace
@@ -251,13 +329,9 @@ gfft_status gfft_plan_create(gfft_plan** out, int64_t n, gfft_dtype dtype, int64
     const int64_t k = n / 2 + 1;
     if (batch > (int64_t(1) << 62) / (slab_x * n * k * 2 * 8)) return GFFT_E_UNSUPPORTED;
 
-    int count = 0;
-    if (hipGetDeviceCount(&count) != hipSuccess || count < 1) return GFFT_E_NO_DEVICE;
     int dev = 0;
-    if (hipGetDevice(&dev) != hipSuccess) return GFFT_E_HIP;
-    hipDeviceProp_t prop;
-    if (hipGetDeviceProperties(&prop, dev) != hipSuccess) return GFFT_E_HIP;
-    if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0) return GFFT_E_NO_DEVICE;
+    gfft_status st = usable_device(&dev);
+    if (st != GFFT_OK) return st;
 
     gfft_plan* p = new (std::nothrow) gfft_plan;
     if (!p) return GFFT_E_NOMEM;
@@ -276,31 +350,82 @@ gfft_status gfft_plan_create(gfft_plan** out, int64_t n, gfft_dtype dtype, int64
     p->flags = flags;
     p->device = dev;
     p->tw = nullptr;
+    p->zrows = slab_x * n;
+    p->pencil = false;
+    p->pr = p->p;
+    p->pc = 1;
+    p->col = 0;
+    p->w = k;
+    p->g = 1;
+    p->lg_w0 = 0;
+    p->lg_g = 0;
+    if ((st = upload_twiddles(p)) != GFFT_OK) {
+        delete p;
+        return st;
+    }
+    *out = p;
+    return GFFT_OK;
+}
 
-    // FP64 twiddles, rounded once to the working precision.
-    const size_t bytes = size_t(n) * 2 * (dtype == GFFT_F64 ? 8 : 4);
-    std::vector<unsigned char> host(bytes);
-    for (int64_t m = 0; m < n; ++m) {
-        double re, im;
-        unit_root(m, n, &re, &im);
-        if (dtype == GFFT_F64) {
-            double* h = reinterpret_cast<double*>(host.data());
-            h[2 * m] = re;
-            h[2 * m + 1] = im;
-        } else {
-            float* h = reinterpret_cast<float*>(host.data());
-            h[2 * m] = float(re);
-            h[2 * m + 1] = float(im);
-        }
-    }
-    if (hipMalloc(&p->tw, bytes) != hipSuccess) {
+gfft_status gfft_pencil_plan_create(gfft_plan** out, int64_t n, gfft_dtype dtype,
+                                    int64_t grid_r, int64_t grid_c, int64_t col,
+                                    int64_t batch, uint32_t flags) {
+    if (!out) return GFFT_E_INVALID_ARG;
+    *out = nullptr;
+    if (dtype != GFFT_F64 && dtype != GFFT_F32) return GFFT_E_INVALID_ARG;
+    if (flags & ~kKnownFlags) return GFFT_E_INVALID_ARG;
+    if (batch < 1 || n < 1 || grid_r < 1 || grid_c < 1) return GFFT_E_INVALID_ARG;
+    if (col < 0 || col >= grid_c) return GFFT_E_INVALID_ARG;
+    if (!pow2(n) || n < 16 || n > 4096) return GFFT_E_UNSUPPORTED;
+    if (!pow2(grid_r) || !pow2(grid_c)) return GFFT_E_INVALID_ARG;
+    // kz is cut into grid_c chunks of N/(2 grid_c) bins; the second exchange
+    // moves whole first-exchange blocks only when grid_r <= grid_c.
+    if (grid_c > n / 2 || grid_r > grid_c) return GFFT_E_UNSUPPORTED;
+    const uint32_t mf = flags & (GFFT_MFMA_BF16X2 | GFFT_MFMA_BF16X3);
+    if (mf == (GFFT_MFMA_BF16X2 | GFFT_MFMA_BF16X3)) return GFFT_E_INVALID_ARG;
+    if (mf && (dtype != GFFT_F32 || n < 32)) return GFFT_E_UNSUPPORTED;
+    if (flags & (GFFT_FUSE_PACK | GFFT_INPLACE | GFFT_PACK_PAPER_ORDER)) return GFFT_E_UNSUPPORTED;
+    const int64_t k = n / 2 + 1, xr = n / grid_r, yc = n / grid_c;
+    const int64_t w = n / (2 * grid_c) + (col == grid_c - 1 ? 1 : 0);
+    // every buffer (real rows, first-exchange order, y/x pencil) must stay
+    // addressable with 64-bit byte offsets
+    int64_t item = xr * yc * n * 8;
+    if (xr * yc * k * 16 > item) item = xr * yc * k * 16;
+    if (grid_c * xr * yc * w * 16 > item) item = grid_c * xr * yc * w * 16;
+    if (batch > (int64_t(1) << 62) / item) return GFFT_E_UNSUPPORTED;
+
+    int dev = 0;
+    gfft_status st = usable_device(&dev);
+    if (st != GFFT_OK) return st;
+    gfft_plan* p = new (std::nothrow) gfft_plan;
+    if (!p) return GFFT_E_NOMEM;
+    p->n = n;
+    p->x = xr;
+    p->y = yc;
+    p->p = grid_r * grid_c;
+    p->batch = batch;
+    p->k = k;
+    p->rs = n;
+    p->lg_n = ilog2(n);
+    p->lg_x = ilog2(xr);
+    p->lg_y = ilog2(yc);
+    p->lg_p = ilog2(p->p);
+    p->dtype = dtype;
+    p->flags = flags;
+    p->device = dev;
+    p->tw = nullptr;
+    p->zrows = xr * yc;
+    p->pencil = true;
+    p->pr = grid_r;
+    p->pc = grid_c;
+    p->col = col;
+    p->w = w;
+    p->g = grid_c / grid_r;
+    p->lg_w0 = ilog2(n / (2 * grid_c));
+    p->lg_g = ilog2(p->g);
+    if ((st = upload_twiddles(p)) != GFFT_OK) {
         delete p;
-        return GFFT_E_NOMEM;
-    }
-    if (hipMemcpy(p->tw, host.data(), bytes, hipMemcpyHostToDevice) != hipSuccess) {
-        (void)hipFree(p->tw);
-        delete p;
-        return GFFT_E_HIP;
+        return st;
     }
     *out = p;
     return GFFT_OK;
@@ -323,8 +448,18 @@ gfft_status gfft_plan_query(const gfft_plan* p, gfft_plan_sizes* s) {
     s->k = p->k;
     s->real_bytes = real_bytes(p);
     s->complex_bytes = cplx_bytes(p);
-    s->pencil_bytes = p->batch * p->n * p->y * p->k * 2 * elt(p);
-    s->chunk_bytes = p->x * p->y * p->k * 2 * elt(p);
+    if (p->pencil) {
+        s->pencil_bytes = p->batch * p->pc * p->x * p->y * p->w * 2 * elt(p);
+        s->chunk_bytes = p->x * p->y * p->w * 2 * elt(p);
+    } else {
+        s->pencil_bytes = p->batch * p->n * p->y * p->k * 2 * elt(p);
+        s->chunk_bytes = p->x * p->y * p->k * 2 * elt(p);
+    }
+    s->grid_r = p->pr;
+    s->grid_c = p->pc;
+    s->col = p->col;
+    s->y_local = p->pencil ? p->y : p->n;
+    s->kz_width = p->w;
     return GFFT_OK;
 }
 
@@ -350,6 +485,7 @@ gfft_status gfft_exec_r2c_adjoint(const gfft_plan* p, void* in, void* out, doubl
 gfft_status gfft_pack_slab_for_alltoall(const gfft_plan* p, const void* src, void* dst,
                                         void* stream) {
     if (!p) return GFFT_E_INVALID_ARG;
+    if (p->pencil) return GFFT_E_UNSUPPORTED;
     gfft_status st = check_ptr(src);
     if (st != GFFT_OK || (st = check_ptr(dst)) != GFFT_OK) return st;
     if (overlap(src, cplx_bytes(p), dst, cplx_bytes(p))) return GFFT_E_INVALID_ARG;
@@ -363,6 +499,7 @@ gfft_status gfft_pack_slab_for_alltoall(const gfft_plan* p, const void* src, voi
 gfft_status gfft_unpack_slab_from_alltoall(const gfft_plan* p, const void* src, void* dst,
                                            void* stream) {
     if (!p) return GFFT_E_INVALID_ARG;
+    if (p->pencil) return GFFT_E_UNSUPPORTED;
     gfft_status st = check_ptr(src);
     if (st != GFFT_OK || (st = check_ptr(dst)) != GFFT_OK) return st;
     if (overlap(src, cplx_bytes(p), dst, cplx_bytes(p))) return GFFT_E_INVALID_ARG;

@@ -15,10 +15,16 @@ namespace gfft {
 // then share the same bytes).
 // paper != 0 selects the chunk order of the paper's local xy transpose,
 // [p][N/p][X] = the slab transposed to [N][X] (row (x_l, y) at y X + x_l).
+// pencil != 0 selects the first-exchange order of a pencil plan instead: the
+// K bins of row r = item * 2^lg_rows + r_l are cut into pc = pc_last + 1
+// chunks, chunk c holding kz in [c w, (c+1) w) with w = 2^lg_w = N/(2 pc)
+// and the last chunk also kz = N/2; chunk c is a [2^lg_rows][w_c] block at
+// item * 2^lg_rows * K + c * 2^lg_rows * w.
 struct row_map {
     int lg_n, lg_x, lg_y;
     int64_t rs;
     int paper;
+    int pencil = 0, lg_rows = 0, lg_w = 0, pc_last = 0;
 };
 
 // Address of element (b, n, m) of a batch of strided lines:

@@ -48,6 +48,16 @@ __device__ __forceinline__ int64_t map_row(int64_t r, row_map m) {
     return (b << (m.lg_x + m.lg_n)) + ((((j << m.lg_x) + xl)) << m.lg_y) + yl;
 }
 
+// Offset (in complex values) of bin k of row r in a pencil plan's
+// first-exchange order (row_map::pencil).
+__device__ __forceinline__ int64_t pencil_bin(int64_t r, int k, int K, const row_map& m) {
+    const int64_t item = r >> m.lg_rows;
+    const int64_t rl = r & ((int64_t(1) << m.lg_rows) - 1);
+    const int c = (k >> m.lg_w) < m.pc_last ? (k >> m.lg_w) : m.pc_last;
+    const int64_t wc = (int64_t(1) << m.lg_w) + (c == m.pc_last ? 1 : 0);
+    return ((item * K + (int64_t(c) << m.lg_w)) << m.lg_rows) + rl * wc + (k - (c << m.lg_w));
+}
+
 // Consecutive workgroup ids are dealt round-robin to the 8 XCDs, each with
 // its own L2.  Remap so that XCD x works through one contiguous range of
 // tiles: neighbouring tiles share cache lines at their edges.
@@ -88,7 +98,8 @@ struct zcfg {
 // ALIAS: `in` and `out` are the same buffer (in-place plans).  Each row is
 // read completely before the first barrier and written after the last one,
 // so a row is never overwritten before all of it has been loaded.
-template <typename T, int N, int EMAX, int THREADS, bool REMAP, bool NTS, bool ALIAS>
+template <typename T, int N, int EMAX, int THREADS, bool REMAP, bool NTS, bool ALIAS,
+          bool PENCIL = false>
 __device__ __forceinline__ void z_r2c_body(
     const T* in, cx<T>* out, const cx<T>* __restrict__ tw,
     int64_t rows, row_map map, T mul_edge, T mul_int) {
@@ -124,9 +135,11 @@ __device__ __forceinline__ void z_r2c_body(
     // stores through a pointer that may alias `in` would otherwise keep the
     // twiddle loads from being issued early.
     const cx<T> x_m{(a[0].x - a[0].y) * mul_edge, T(0)};
-    cx<T>* dst = out + map_row(row, map) * K;
+    cx<T>* dst = out + (PENCIL ? 0 : map_row(row, map) * K);
     auto put = [&](int k, cx<T> v) {
-        if constexpr (NTS) {
+        if constexpr (PENCIL) {
+            out[pencil_bin(row, k, K, map)] = v;
+        } else if constexpr (NTS) {
             __builtin_nontemporal_store(v.x, &dst[k].x);
             __builtin_nontemporal_store(v.y, &dst[k].y);
         } else {
@@ -150,7 +163,7 @@ __device__ __forceinline__ void z_r2c_body(
 #pragma unroll
         for (int m = 0; m < E; ++m) put(t + m * TPT, a[m]);
     }
-    if (t == 0) dst[M] = x_m;
+    if (t == 0) put(M, x_m);
 }
 
 template <typename T, int N, int EMAX, int THREADS, bool REMAP, bool NTS>
@@ -167,8 +180,17 @@ __global__ __launch_bounds__((zshape<N / 2, EMAX, THREADS>::NT)) void k_z_r2c_in
     z_r2c_body<T, N, EMAX, THREADS, REMAP, NTS, true>(in, out, tw, rows, map, mul_edge, mul_int);
 }
 
+// Pencil plans: bins scattered to the first exchange's chunks.
+template <typename T, int N, int EMAX, int THREADS, bool REMAP>
+__global__ __launch_bounds__((zshape<N / 2, EMAX, THREADS>::NT)) void k_z_r2c_pencil(
+    const T* __restrict__ in, cx<T>* __restrict__ out, const cx<T>* __restrict__ tw,
+    int64_t rows, row_map map, T mul_edge, T mul_int) {
+    z_r2c_body<T, N, EMAX, THREADS, REMAP, false, false, true>(in, out, tw, rows, map, mul_edge,
+                                                               mul_int);
+}
+
 // ---------------------------------------------------------------- z C2R
-template <typename T, int N, int EMAX, int THREADS, bool REMAP, bool NTS>
+template <typename T, int N, int EMAX, int THREADS, bool REMAP, bool NTS, bool PENCIL = false>
 __device__ __forceinline__ void z_c2r_body(
     const cx<T>* in, T* out, const cx<T>* __restrict__ tw,
     int64_t rows, row_map map, T mul_edge, T mul_int) {
@@ -190,10 +212,18 @@ __device__ __forceinline__ void z_c2r_body(
     // multipliers (scale, and 1/w for the adjoint).
     // Rows past the end (last workgroup) load the last row and discard it.
     cx<T> g[E];
-    const cx<T>* src = in + map_row(valid ? row : rows - 1, map) * K;
+    cx<T> g_m;
+    const int64_t lrow = valid ? row : rows - 1;
+    if constexpr (PENCIL) {
 #pragma unroll
-    for (int m = 0; m < E; ++m) g[m] = src[t + m * TPT];
-    cx<T> g_m = t == 0 ? src[M] : cx<T>{T(0), T(0)};
+        for (int m = 0; m < E; ++m) g[m] = in[pencil_bin(lrow, t + m * TPT, K, map)];
+        g_m = t == 0 ? in[pencil_bin(lrow, M, K, map)] : cx<T>{T(0), T(0)};
+    } else {
+        const cx<T>* src = in + map_row(lrow, map) * K;
+#pragma unroll
+        for (int m = 0; m < E; ++m) g[m] = src[t + m * TPT];
+        g_m = t == 0 ? src[M] : cx<T>{T(0), T(0)};
+    }
 #pragma unroll
     for (int m = 0; m < E; ++m) {
         const int k = t + m * TPT;
@@ -244,6 +274,14 @@ __global__ __launch_bounds__((zshape<N / 2, EMAX, THREADS>::NT)) void k_z_c2r_in
     const cx<T>* in, T* out, const cx<T>* __restrict__ tw,
     int64_t rows, row_map map, T mul_edge, T mul_int) {
     z_c2r_body<T, N, EMAX, THREADS, REMAP, NTS>(in, out, tw, rows, map, mul_edge, mul_int);
+}
+
+// Pencil plans: bins gathered from the first exchange's chunks.
+template <typename T, int N, int EMAX, int THREADS, bool REMAP, bool NTS>
+__global__ __launch_bounds__((zshape<N / 2, EMAX, THREADS>::NT)) void k_z_c2r_pencil(
+    const cx<T>* __restrict__ in, T* __restrict__ out, const cx<T>* __restrict__ tw,
+    int64_t rows, row_map map, T mul_edge, T mul_int) {
+    z_c2r_body<T, N, EMAX, THREADS, REMAP, NTS, true>(in, out, tw, rows, map, mul_edge, mul_int);
 }
 
 // ---------------------------------------------------------------- y / x C2C
@@ -476,7 +514,11 @@ static hipError_t z_r2c_n(const void* in, void* out, const void* tw, int64_t row
     const int64_t blocks = (rows + Z::RPB - 1) / Z::RPB;
     if (blocks == 0) return hipSuccess;
     if (blocks > kMaxBlocks) return hipErrorInvalidValue;
-    if (in == out)
+    if (map.pencil)
+        hipLaunchKernelGGL((k_z_r2c_pencil<T, N, C::EMAX, C::THREADS, C::REMAP>), dim3(blocks),
+                           dim3(Z::NT), 0, s, static_cast<const T*>(in), static_cast<cx<T>*>(out),
+                           static_cast<const cx<T>*>(tw), rows, map, T(me), T(mi));
+    else if (in == out)
         hipLaunchKernelGGL((k_z_r2c_inplace<T, N, C::EMAX, C::THREADS, C::REMAP, C::NTS>),
                            dim3(blocks), dim3(Z::NT), 0, s, static_cast<const T*>(in),
                            static_cast<cx<T>*>(out), static_cast<const cx<T>*>(tw), rows, map,
@@ -496,7 +538,12 @@ static hipError_t z_c2r_n(const void* in, void* out, const void* tw, int64_t row
     const int64_t blocks = (rows + Z::RPB - 1) / Z::RPB;
     if (blocks == 0) return hipSuccess;
     if (blocks > kMaxBlocks) return hipErrorInvalidValue;
-    if (in == out)
+    if (map.pencil)
+        hipLaunchKernelGGL((k_z_c2r_pencil<T, N, C::EMAX, C::THREADS, C::REMAP, C::NTS>),
+                           dim3(blocks), dim3(Z::NT), 0, s, static_cast<const cx<T>*>(in),
+                           static_cast<T*>(out), static_cast<const cx<T>*>(tw), rows, map,
+                           T(me), T(mi));
+    else if (in == out)
         hipLaunchKernelGGL((k_z_c2r_inplace<T, N, C::EMAX, C::THREADS, C::REMAP, C::NTS>),
                            dim3(blocks), dim3(Z::NT), 0, s, static_cast<const cx<T>*>(in),
                            static_cast<T*>(out), static_cast<const cx<T>*>(tw), rows, map,

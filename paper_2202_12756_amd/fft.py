@@ -272,3 +272,115 @@ class Plan:
             self.close()
         except Exception:
             pass
+
+
+class PencilPlan:
+    """Rank (r, c)'s share of an N^3 real FFT on a pr x pc pencil grid.
+
+    Real pencil [batch, X, Y, N] (X = N/pr, Y = N/pc, z fastest).  The z pass
+    writes the half spectrum in first-exchange order, ``send_shape`` =
+    [batch, X*Y*K]: chunk c' = kz in ``kz_range(c')``, a [X, Y, w_c'] block
+    (``chunk`` gives views).  After exchange 1 the y pass runs on the
+    y-pencil [batch, pc, X, Y, w] (block c' from rank (r, c')); after
+    exchange 2 the x pass runs on the x-pencil [batch, pr, g, X, Y, w]
+    (g = pc/pr; block r from rank (r, c) = its y-pencil blocks
+    [r' g, (r'+1) g) for destination r').  Requires pr <= pc <= N/2.
+    """
+
+    _check = Plan._check
+
+    def __init__(self, n: int, dtype=torch.float64, grid=(1, 1), col: int = 0,
+                 batch: int = 1, device=None, mfma_terms: int = 0):
+        if dtype not in _REAL:
+            raise TypeError("dtype must be torch.float64 or torch.float32")
+        self.n = int(n)
+        self.dtype = dtype
+        self.cdtype = _CPLX[dtype]
+        self.pr, self.pc = (int(v) for v in grid)
+        self.col = int(col)
+        self.batch = int(batch)
+        self.device = torch.device(device if device is not None else "cuda")
+        if int(mfma_terms) not in (0, 2, 3):
+            raise ValueError("mfma_terms must be 0, 2 or 3")
+        flags = {0: 0, 2: _lib.GFFT_MFMA_BF16X2, 3: _lib.GFFT_MFMA_BF16X3}[int(mfma_terms)]
+        with torch.cuda.device(self.device):
+            st, h = _lib.gfft_pencil_plan_create(self.n, _REAL[dtype], self.pr, self.pc,
+                                                 self.col, self.batch, flags)
+        _lib.check(st, "gfft_pencil_plan_create")
+        self._h = h
+        st, s = _lib.gfft_plan_query(h)
+        _lib.check(st, "gfft_plan_query")
+        self.sizes = {f: getattr(s, f) for f, _ in _lib.gfft_plan_sizes._fields_}
+        self.k = s.k
+        self.x = s.slab_x
+        self.y = s.y_local
+        self.w = s.kz_width
+        self.w0 = self.n // (2 * self.pc)
+        self.g = self.pc // self.pr
+
+    def kz_range(self, c: int):
+        """The kz bins [k0, k1) that column c holds after exchange 1."""
+        k0 = c * self.w0
+        return k0, k0 + self.w0 + (1 if c == self.pc - 1 else 0)
+
+    @property
+    def real_shape(self):
+        return (self.batch, self.x, self.y, self.n)
+
+    @property
+    def send_shape(self):
+        return (self.batch, self.x * self.y * self.k)
+
+    @property
+    def ypencil_shape(self):
+        return (self.batch, self.pc, self.x, self.y, self.w)
+
+    @property
+    def xpencil_shape(self):
+        return (self.batch, self.pr, self.g, self.x, self.y, self.w)
+
+    def chunk(self, send: torch.Tensor, c: int) -> torch.Tensor:
+        """View [batch, X, Y, w_c] of chunk c of a first-exchange buffer."""
+        k0, k1 = self.kz_range(c)
+        rows = self.x * self.y
+        return send[:, rows * k0: rows * k1].view(self.batch, self.x, self.y, k1 - k0)
+
+    def _n(self, shape):
+        out = 1
+        for v in shape:
+            out *= v
+        return out
+
+    def z_r2c(self, x, out=None, scale: float = 1.0, weighted: bool = False):
+        out = (torch.empty(self.send_shape, dtype=self.cdtype, device=self.device)
+               if out is None else out)
+        a = self._check(x, self.dtype, self._n(self.real_shape), "input")
+        b = self._check(out, self.cdtype, self._n(self.send_shape), "output")
+        _lib.check(_lib.gfft_exec_z_r2c(self._h, a, b, float(scale), int(weighted),
+                                        _stream(self.device)), "gfft_exec_z_r2c")
+        return out
+
+    def y_c2c(self, ypencil, sign: int):
+        a = self._check(ypencil, self.cdtype, self._n(self.ypencil_shape), "y-pencil")
+        _lib.check(_lib.gfft_exec_y_c2c(self._h, a, int(sign), _stream(self.device)),
+                   "gfft_exec_y_c2c")
+        return ypencil
+
+    def x_c2c(self, xpencil, sign: int):
+        a = self._check(xpencil, self.cdtype, self._n(self.xpencil_shape), "x-pencil")
+        _lib.check(_lib.gfft_exec_x_c2c(self._h, a, int(sign), _stream(self.device)),
+                   "gfft_exec_x_c2c")
+        return xpencil
+
+    def z_c2r(self, g, out=None, scale: float = 1.0, weighted: bool = False):
+        """Inverse z pass from first-exchange order (reads ``g``)."""
+        out = (torch.empty(self.real_shape, dtype=self.dtype, device=self.device)
+               if out is None else out)
+        a = self._check(g, self.cdtype, self._n(self.send_shape), "input")
+        b = self._check(out, self.dtype, self._n(self.real_shape), "output")
+        _lib.check(_lib.gfft_exec_z_c2r(self._h, a, b, float(scale), int(weighted),
+                                        _stream(self.device)), "gfft_exec_z_c2r")
+        return out
+
+    close = Plan.close
+    __del__ = Plan.__del__

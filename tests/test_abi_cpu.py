@@ -76,9 +76,43 @@ def test_plan_create_validates_on_host(args, expect):
         assert not h.value
 
 
+@pytest.mark.parametrize("args,expect", [
+    ((64, 0, 2, 4, 1, 1, 0), None),                            # valid
+    ((64, 0, 8, 16, 15, 1, 0), None),                          # p = 128 > N
+    ((64, 0, 1, 1, 0, 1, 0), None),                            # one rank
+    ((64, 0, 4, 2, 0, 1, 0), _lib.GFFT_E_UNSUPPORTED),         # pr > pc
+    ((64, 0, 2, 64, 0, 1, 0), _lib.GFFT_E_UNSUPPORTED),        # pc > N/2
+    ((64, 0, 3, 4, 0, 1, 0), _lib.GFFT_E_INVALID_ARG),         # pr not 2^m
+    ((64, 0, 2, 4, 4, 1, 0), _lib.GFFT_E_INVALID_ARG),         # col >= pc
+    ((64, 0, 2, 4, -1, 1, 0), _lib.GFFT_E_INVALID_ARG),        # col < 0
+    ((64, 0, 0, 4, 0, 1, 0), _lib.GFFT_E_INVALID_ARG),         # pr = 0
+    ((64, 0, 2, 4, 0, 0, 0), _lib.GFFT_E_INVALID_ARG),         # batch 0
+    ((48, 0, 2, 4, 0, 1, 0), _lib.GFFT_E_UNSUPPORTED),         # N not 2^m
+    ((64, 0, 2, 4, 0, 1, 1), _lib.GFFT_E_UNSUPPORTED),         # slab flag
+    ((64, 0, 2, 4, 0, 1, 8), _lib.GFFT_E_UNSUPPORTED),         # in place
+    ((64, 1, 2, 4, 0, 1, 2), None),                            # FP32 + MFMA
+    ((64, 0, 2, 4, 0, 1, 2), _lib.GFFT_E_UNSUPPORTED),         # MFMA needs FP32
+    ((64, 0, 2, 4, 0, 1, 1 << 9), _lib.GFFT_E_INVALID_ARG),    # unknown flag
+    ((4096, 0, 1, 1, 0, 1 << 40, 0), _lib.GFFT_E_UNSUPPORTED), # size overflow
+])
+def test_pencil_plan_create_validates_on_host(args, expect):
+    st, h = _lib.gfft_pencil_plan_create(*args)
+    if expect is None:
+        if not _has_gpu():
+            assert st == _lib.GFFT_E_NO_DEVICE
+            assert not h.value
+        else:
+            assert st == _lib.GFFT_OK
+            assert _lib.gfft_plan_destroy(h) == _lib.GFFT_OK
+    else:
+        assert st == expect
+        assert not h.value
+
+
 def test_null_plan_and_out_pointer():
     lib = _lib.load()
     assert lib.gfft_plan_create(None, 64, 0, 64, 1, 0) == _lib.GFFT_E_INVALID_ARG
+    assert lib.gfft_pencil_plan_create(None, 64, 0, 2, 4, 0, 1, 0) == _lib.GFFT_E_INVALID_ARG
     assert _lib.gfft_plan_destroy(None) == _lib.GFFT_OK
     st, _ = _lib.gfft_plan_query(None)
     assert st == _lib.GFFT_E_INVALID_ARG

@@ -1,0 +1,127 @@
+"""GPU parity of pencil plans (section 2, pencil decomposition): every rank
+of a pr x pc grid runs on one GPU in turn, the two exchanges are device
+copies between the ranks' buffers, and each stage is compared with the
+oracle's pencil pipeline; p = pr pc exceeds N in several cases."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from helpers import TOL, host, real_input, rel_l2
+from paper_2202_12756_amd import GfftError, PencilPlan, _lib
+
+pytestmark = pytest.mark.gpu
+
+CASES = [(16, 2, 4), (32, 4, 8), (32, 8, 16), (64, 2, 2), (64, 4, 16), (128, 4, 4)]
+
+
+def _plans(n, pr, pc, dtype, batch=1, mfma_terms=0):
+    return [PencilPlan(n, dtype, (pr, pc), c, batch, mfma_terms=mfma_terms) for c in range(pc)]
+
+
+@pytest.mark.parametrize("dtype,mfma", [(torch.float64, 0), (torch.float32, 0)],
+                         ids=["f64", "f32"])
+@pytest.mark.parametrize("n,pr,pc", CASES)
+def test_pencil_forward_and_inverse(n, pr, pc, dtype, mfma):
+    _pipeline(n, pr, pc, dtype, mfma)
+
+
+def test_pencil_matrix_core_stage():
+    """FP32 with the radix-16 stage of the y and x passes on the matrix
+    cores (3 BF16 terms, FP32-level accuracy)."""
+    _pipeline(64, 2, 4, torch.float32, 3)
+
+
+def _pipeline(n, pr, pc, dtype, mfma):
+    f, fref = real_input((n, n, n), 1200 + n + pr + pc, dtype)
+    plans = _plans(n, pr, pc, dtype, mfma_terms=mfma)
+    x, y, g = n // pr, n // pc, pc // pr
+    F = oracle.r2c3d(fref)
+    # step 1: z R2C into first-exchange order, per rank
+    sends = {}
+    for r in range(pr):
+        for c in range(pc):
+            part = f[r * x:(r + 1) * x, c * y:(c + 1) * y].contiguous().view(plans[c].real_shape)
+            sends[r, c] = plans[c].z_r2c(part)
+    torch.cuda.synchronize()
+    zref = oracle.pencil_send(oracle.r2c_last(fref[:x, :y]), pc)
+    assert rel_l2(host(sends[0, 0])[0], zref) <= TOL[dtype]
+    # exchange 1 and the y pass
+    ypen = {}
+    for r in range(pr):
+        for c in range(pc):
+            yp = torch.empty(plans[c].ypencil_shape, dtype=plans[c].cdtype, device="cuda")
+            for cp in range(pc):
+                yp[:, cp].copy_(plans[cp].chunk(sends[r, cp], c))
+            ypen[r, c] = plans[c].y_c2c(yp, -1)
+    torch.cuda.synchronize()
+    yref = oracle.pencil_y_c2c(oracle.pencil_exchange1(
+        [oracle.pencil_send(oracle.r2c_last(fref[:x, c * y:(c + 1) * y]), pc) for c in range(pc)],
+        x, y)[pc - 1], -1)
+    assert rel_l2(host(ypen[0, pc - 1])[0], yref) <= TOL[dtype]
+    # exchange 2 and the x pass
+    xpen = {}
+    for c in range(pc):
+        for rp in range(pr):
+            xp = torch.empty(plans[c].xpencil_shape, dtype=plans[c].cdtype, device="cuda")
+            for r in range(pr):
+                xp[:, r].copy_(ypen[r, c][:, rp * g:(rp + 1) * g])
+            xpen[rp, c] = plans[c].x_c2c(xp, -1)
+    torch.cuda.synchronize()
+    for (rp, c), got in xpen.items():
+        k0, k1 = oracle.pencil_kz_range(n, pc, c)
+        r_, g_, x_, y_, k_ = np.meshgrid(np.arange(pr), np.arange(g), np.arange(x),
+                                         np.arange(y), np.arange(k1 - k0), indexing="ij")
+        want = F[r_ * x + x_, rp * (n // pr) + g_ * y + y_, k0 + k_]
+        assert rel_l2(host(got)[0], want) <= TOL[dtype], (rp, c)
+    # inverse: x^-1, exchange 2 back, y^-1, exchange 1 back, z C2R
+    for key in xpen:
+        plans[key[1]].x_c2c(xpen[key], +1)
+    for c in range(pc):
+        for r in range(pr):
+            for rp in range(pr):
+                ypen[r, c][:, rp * g:(rp + 1) * g].copy_(xpen[rp, c][:, r])
+            plans[c].y_c2c(ypen[r, c], +1)
+    out = torch.empty_like(f)
+    for r in range(pr):
+        for cp in range(pc):
+            back = torch.empty(plans[cp].send_shape, dtype=plans[cp].cdtype, device="cuda")
+            for c in range(pc):
+                plans[cp].chunk(back, c).copy_(ypen[r, c][:, cp])
+            real = plans[cp].z_c2r(back, scale=1.0 / n ** 3)
+            out[r * x:(r + 1) * x, cp * y:(cp + 1) * y] = real[0]
+    torch.cuda.synchronize()
+    assert rel_l2(host(out), fref) <= TOL[dtype]
+
+
+def test_pencil_batch_and_weighted_z_pass():
+    """batch = 2 grids back to back; the adjoint's bin weights on the z pass."""
+    n, pr, pc = 32, 2, 4
+    p = PencilPlan(n, torch.float64, (pr, pc), 1, batch=2)
+    h, href = real_input(p.real_shape, 1300, torch.float64)
+    out = p.z_r2c(h, scale=0.5, weighted=True)
+    torch.cuda.synchronize()
+    w = oracle.half_weights(n)
+    want = oracle.pencil_send(0.5 * w * oracle.r2c_last(href), pc)
+    assert rel_l2(host(out), want) <= 1e-13
+    back = p.z_c2r(out.clone(), scale=1.0, weighted=True)
+    torch.cuda.synchronize()
+    # C2R(G / w) of w R2C(h) / 2 = n h / 2 along z
+    assert rel_l2(host(back), 0.5 * n * href) <= 1e-13
+
+
+def test_pencil_plan_rejects_slab_entry_points():
+    p = PencilPlan(32, torch.float64, (2, 4), 0)
+    a = torch.zeros(p.real_shape, dtype=torch.float64, device="cuda")
+    b = torch.zeros(p.send_shape, dtype=torch.complex128, device="cuda")
+    s = torch.cuda.current_stream().cuda_stream
+    assert _lib.gfft_exec_r2c(p._h, a.data_ptr(), b.data_ptr(), s) == _lib.GFFT_E_UNSUPPORTED
+    assert _lib.gfft_exec_c2r(p._h, b.data_ptr(), a.data_ptr(), 1.0, s) == _lib.GFFT_E_UNSUPPORTED
+    assert (_lib.gfft_pack_slab_for_alltoall(p._h, b.data_ptr(), a.data_ptr(), s)
+            == _lib.GFFT_E_UNSUPPORTED)
+    sz = p.sizes
+    assert sz["grid_r"] == 2 and sz["grid_c"] == 4 and sz["col"] == 0
+    assert sz["kz_width"] == 4 and sz["y_local"] == 8 and sz["slab_x"] == 16
+    assert sz["pencil_bytes"] == 4 * 16 * 8 * 4 * 16
+    with pytest.raises(GfftError):
+        PencilPlan(32, torch.float64, (8, 4), 0)

@@ -1,0 +1,109 @@
+"""The oracle's pencil layouts (section 2, pencil decomposition), pinned to
+the full-grid forward transform (itself pinned to brute force, closed forms
+and the paper's Eq. 5) and to the identities of the exchanges."""
+import numpy as np
+import torch
+import pytest
+
+import oracle
+import synth
+
+CASES = [(16, 1, 1), (16, 1, 2), (16, 2, 2), (16, 2, 4), (16, 4, 8), (32, 2, 8), (32, 8, 16)]
+
+
+def test_kz_ranges_partition_the_half_spectrum():
+    for n in (16, 32, 64, 1024):
+        k = n // 2 + 1
+        pc = 1
+        while pc <= n // 2:
+            seen = np.zeros(k, dtype=int)
+            for c in range(pc):
+                k0, k1 = oracle.pencil_kz_range(n, pc, c)
+                assert k1 - k0 == n // (2 * pc) + (c == pc - 1)
+                seen[k0:k1] += 1
+            assert np.all(seen == 1)
+            pc *= 2
+
+
+@pytest.mark.parametrize("pc", [1, 2, 8])
+def test_send_order_round_trip_and_chunk_contents(pc):
+    n, x, y = 16, 4, 2
+    k = n // 2 + 1
+    rows = np.arange(2 * x * y * k).reshape(2, x, y, k).astype(np.complex128)
+    flat = oracle.pencil_send(rows, pc)
+    assert flat.shape == (2, x * y * k)
+    assert np.array_equal(oracle.pencil_unsend(flat, x, y, pc), rows)
+    # chunk c' begins at X Y k0 and is the [X][Y][w] block of its bins
+    for c in range(pc):
+        k0, k1 = oracle.pencil_kz_range(n, pc, c)
+        blk = flat[:, x * y * k0:x * y * k1].reshape(2, x, y, k1 - k0)
+        assert np.array_equal(blk, rows[..., k0:k1])
+
+
+def _forward(f, n, pr, pc):
+    """The pencil pipeline on the oracle: per rank z R2C, exchange 1, y DFT,
+    exchange 2, x DFT.  Returns {(r, c): x-pencil}."""
+    x, y = n // pr, n // pc
+    xp = {}
+    ys = {}
+    for r in range(pr):
+        sends = [oracle.pencil_send(oracle.r2c_last(f[r * x:(r + 1) * x, c * y:(c + 1) * y]), pc)
+                 for c in range(pc)]
+        for c, yp in enumerate(oracle.pencil_exchange1(sends, x, y)):
+            ys[r, c] = oracle.pencil_y_c2c(yp, -1)
+    for c in range(pc):
+        for rp, xpen in enumerate(oracle.pencil_exchange2([ys[r, c] for r in range(pr)], pr)):
+            xp[rp, c] = oracle.pencil_x_c2c(xpen, -1)
+    return xp, ys
+
+
+@pytest.mark.parametrize("n,pr,pc", CASES)
+def test_pencil_pipeline_equals_full_transform(n, pr, pc):
+    """Every x-pencil element equals F(x = r X + x_l, y = r' N/pr + g_l Y +
+    y_l, kz = c w0 + kz_l) of the full-grid transform; p = pr pc exceeds N
+    in the last cases."""
+    f = synth.uniform((n, n, n), 900 + n + pr + pc, torch.float64, "cpu").numpy()
+    F = oracle.r2c3d(f)
+    x, y, g, w0 = n // pr, n // pc, pc // pr, n // (2 * pc)
+    xp, _ = _forward(f, n, pr, pc)
+    for (rp, c), got in xp.items():
+        k0, k1 = oracle.pencil_kz_range(n, pc, c)
+        r_, g_, x_, y_, k_ = np.meshgrid(np.arange(pr), np.arange(g), np.arange(x), np.arange(y),
+                                         np.arange(k1 - k0), indexing="ij")
+        want = F[r_ * x + x_, rp * (n // pr) + g_ * y + y_, c * w0 + k_]
+        assert got.shape == (pr, g, x, y, k1 - k0)
+        assert np.max(np.abs(got - want)) <= 1e-12 * np.max(np.abs(F))
+
+
+@pytest.mark.parametrize("n,pr,pc", CASES[2:])
+def test_pencil_round_trip(n, pr, pc):
+    """Backwards through x^-1, exchange 2 back, y^-1, exchange 1 back and
+    the z C2R gives N^3 f."""
+    f = synth.uniform((n, n, n), 950 + n, torch.float64, "cpu").numpy()
+    x, y = n // pr, n // pc
+    xp, _ = _forward(f, n, pr, pc)
+    out = np.empty_like(f)
+    for c in range(pc):
+        back = oracle.pencil_exchange2_back([oracle.pencil_x_c2c(xp[rp, c], +1)
+                                             for rp in range(pr)])
+        for r in range(pr):
+            xp[r, c] = oracle.pencil_y_c2c(back[r], +1)          # reuse as y-pencils
+    for r in range(pr):
+        sends = oracle.pencil_exchange1_back([xp[r, c] for c in range(pc)])
+        for c in range(pc):
+            rows = oracle.pencil_unsend(sends[c], x, y, pc)
+            out[r * x:(r + 1) * x, c * y:(c + 1) * y] = oracle.c2r_last(rows, n)
+    assert np.max(np.abs(out / n ** 3 - f)) <= 1e-13
+
+
+def test_exchange_back_inverts_exchange():
+    rng = np.random.default_rng(5)
+    x, y, pc, pr = 2, 4, 4, 2
+    k = 9
+    sends = [rng.standard_normal((x * y * k,)) + 0j for _ in range(pc)]
+    ys = oracle.pencil_exchange1(sends, x, y)
+    for a, b in zip(oracle.pencil_exchange1_back(ys), sends):
+        assert np.array_equal(a, b)
+    ypens = [rng.standard_normal((pc, x, y, 3)) for _ in range(pr)]
+    for a, b in zip(oracle.pencil_exchange2_back(oracle.pencil_exchange2(ypens, pr)), ypens):
+        assert np.array_equal(a, b)

@@ -219,6 +219,44 @@ def variants(n: int, steps: int, x64: torch.Tensor, dev) -> dict:
                                                           / 1e9 / PEAK_HBM_GBS, 4)}
     del G, h, p64
     torch.cuda.empty_cache()
+    out.update(pencil_variants(steps, dev))
+    return out
+
+
+def pencil_variants(steps: int, dev) -> dict:
+    """One rank's local forward chain of a pencil-decomposed 4096^3 FP64 grid
+    (z R2C into the first-exchange order, y pass on the received y-pencil,
+    x pass on the received x-pencil; the exchanges are the caller's), for
+    rank (0, 0) of a 16 x 32 grid (512 ranks, the paper's largest count) and
+    of a 64 x 128 grid (8192 ranks > N).  Bytes per pass: z reads the real
+    pencil and writes the first-exchange buffer, y and x read and write their
+    pencil in place."""
+    import synth
+    from paper_2202_12756_amd import PencilPlan
+
+    n, out = 4096, {}
+    for pr, pc in ((16, 32), (64, 128)):
+        p = PencilPlan(n, torch.float64, (pr, pc), 0, device=dev)
+        xr = synth.uniform(p.real_shape, 11, torch.float64, dev)
+        send = torch.empty(p.send_shape, dtype=torch.complex128, device=dev)
+        yp = torch.view_as_complex(synth.uniform(p.ypencil_shape + (2,), 12, torch.float64, dev))
+        xp = torch.view_as_complex(synth.uniform(p.xpencil_shape + (2,), 13, torch.float64, dev))
+        ms = {"z_r2c": time_pairs(lambda: p.z_r2c(xr, send), steps, 2),
+              "y_fwd": time_pairs(lambda: p.y_c2c(yp, -1), steps, 2),
+              "x_fwd": time_pairs(lambda: p.x_c2c(xp, -1), steps, 2)}
+        bts = {"z_r2c": xr.numel() * 8 + send.numel() * 16,
+               "y_fwd": 2 * yp.numel() * 16, "x_fwd": 2 * xp.numel() * 16}
+        total_ms = sum(ms.values())
+        out[f"pencil_4096_{pr}x{pc}_f64"] = {
+            "ranks": pr * pc, "real_pencil": f"{p.x}x{p.y}x{n}", "kz_width": p.w,
+            "pass_ms": {k: round(v, 4) for k, v in ms.items()},
+            "pass_GBps": {k: round(bts[k] / (ms[k] * 1e-3) / 1e9, 1) for k in ms},
+            "chain_ms": round(total_ms, 4),
+            "chain_hbm_roofline_frac": round(sum(bts.values()) / (total_ms * 1e-3) / 1e9
+                                             / PEAK_HBM_GBS, 4),
+        }
+        del p, xr, send, yp, xp
+        torch.cuda.empty_cache()
     return out
 
 

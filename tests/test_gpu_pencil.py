@@ -125,3 +125,52 @@ def test_pencil_plan_rejects_slab_entry_points():
     assert sz["pencil_bytes"] == 4 * 16 * 8 * 4 * 16
     with pytest.raises(GfftError):
         PencilPlan(32, torch.float64, (8, 4), 0)
+
+
+@pytest.mark.parametrize("col", [0, 31])
+def test_pencil_4096_share_sampled(col):
+    """Rank (0, col) of 16 x 32 on 4096^3 FP64, the size the benchmark
+    times: each pass on seeded input, checked on sampled rows and lines
+    that the oracle transforms one by one."""
+    import synth
+    n, pr, pc = 4096, 16, 32
+    p = PencilPlan(n, torch.float64, (pr, pc), col)
+    x, y, w, g = p.x, p.y, p.w, p.g
+    rng = np.random.default_rng(77 + col)
+    # z pass: rows -> first-exchange order
+    xr = synth.uniform(p.real_shape, 21, torch.float64, "cuda")
+    send = p.z_r2c(xr)
+    torch.cuda.synchronize()
+    for _ in range(6):
+        xl, yl = int(rng.integers(x)), int(rng.integers(y))
+        row = xr[0, xl, yl].cpu().numpy()
+        ref = oracle.r2c_last(row)
+        got = np.empty_like(ref)
+        for c in range(pc):
+            k0, k1 = oracle.pencil_kz_range(n, pc, c)
+            got[k0:k1] = p.chunk(send, c)[0, xl, yl].cpu().numpy()
+        assert rel_l2(got, ref) <= 1e-13
+    del xr, send
+    # y pass on a seeded y-pencil: line (x_l, kz_l) runs over (c', y_l)
+    yp = torch.view_as_complex(synth.uniform(p.ypencil_shape + (2,), 22, torch.float64, "cuda"))
+    y0 = yp.clone()
+    p.y_c2c(yp, -1)
+    torch.cuda.synchronize()
+    for _ in range(6):
+        xl, kl = int(rng.integers(x)), int(rng.integers(w))
+        line = y0[0, :, xl, :, kl].reshape(-1).cpu().numpy()
+        ref = oracle.c2c_axis(line, 0, -1)
+        assert rel_l2(yp[0, :, xl, :, kl].reshape(-1).cpu().numpy(), ref) <= 1e-13
+    del yp, y0
+    # x pass on a seeded x-pencil: line (g_l, y_l, kz_l) runs over (r, x_l)
+    xp = torch.view_as_complex(synth.uniform(p.xpencil_shape + (2,), 23, torch.float64, "cuda"))
+    x0 = xp.clone()
+    p.x_c2c(xp, -1)
+    torch.cuda.synchronize()
+    for _ in range(6):
+        gl, yl, kl = int(rng.integers(g)), int(rng.integers(y)), int(rng.integers(w))
+        line = x0[0, :, gl, :, yl, kl].reshape(-1).cpu().numpy()
+        ref = oracle.c2c_axis(line, 0, -1)
+        assert rel_l2(xp[0, :, gl, :, yl, kl].reshape(-1).cpu().numpy(), ref) <= 1e-13
+    del xp, x0
+    torch.cuda.empty_cache()

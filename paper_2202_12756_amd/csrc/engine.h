@@ -151,43 +151,6 @@ struct xch_split {
     }
 };
 
-// The exchange in 2*PARTS rounds: real parts then imaginary parts of the
-// positions in [p N/PARTS, (p+1) N/PARTS) for p = 0..PARTS-1, through a
-// buffer of N/PARTS reals per transform (1/(2 PARTS) of the whole-value
-// buffer).  Writes are predicated on the destination range; the reads of
-// round p are slots m in [p E/PARTS, (p+1) E/PARTS), which lie in that range.
-// (Unpadded layouts only.)
-template <typename T, class Idx, int PARTS>
-struct xch_parts {
-    T* buf;
-    Idx idx;
-    template <int N, int E, int L, int R>
-    __device__ __forceinline__ void run(cx<T> (&a)[E], int t) const {
-        using G = xgeom<N, E, L, R>;
-        constexpr int SEG = N / PARTS, EP = E / PARTS;
-        static_assert(N % PARTS == 0 && E % PARTS == 0, "bad partition");
-        static_assert(Idx::SHIFT == 0, "partitioned exchange uses unpadded layouts");
-#pragma unroll
-        for (int p = 0; p < PARTS; ++p) {
-#pragma unroll
-            for (int comp = 0; comp < 2; ++comp) {
-#pragma unroll
-                for (int s = 0; s < E; ++s) {
-                    const int pos = G::out_pos(t, s) - p * SEG;
-                    if (pos >= 0 && pos < SEG) buf[idx(pos)] = comp ? a[s].y : a[s].x;
-                }
-                __syncthreads();
-#pragma unroll
-                for (int m = p * EP; m < (p + 1) * EP; ++m) {
-                    const T v = buf[idx(t + m * G::TPT - p * SEG)];
-                    if (comp) a[m].y = v; else a[m].x = v;
-                }
-                __syncthreads();
-            }
-        }
-    }
-};
-
 // Run the stages from span L to the end.  `tw` is a table of
 // W_Ntab^m (m = 0..Ntab-1) with Ntab = N * tws; entry idx*tws is W_N^idx.
 template <typename T, int N, int E, int S, int L, class X>

@@ -11,6 +11,9 @@
 //             addresses, so every load and store is a contiguous run of
 //             TC complex values per line position.
 //   pack    : the send-order permutation as a plain copy of contiguous runs.
+// Pencil plans (section 2, pencil decomposition) reuse the same passes: the
+// z pass scatters each row's bins to the first exchange's chunks, and the
+// y/x passes address the received pencils through their line maps.
 // Memory bound: each pass reads and writes its array once.
 #include "cx.h"
 #include "engine.h"
@@ -81,8 +84,9 @@ struct zshape {
 // N = 512, 16 per thread in 128-thread ones for N = 1024 and 2048 (7-8%
 // faster there), 32 per thread for N = 4096; FP64 C2R 16 per thread in
 // 64-thread workgroups; FP32 32 per thread in 64-thread ones.
-// From N = 1024 up, workgroups are dealt to XCDs in contiguous ranges
-// (2-3% on the R2C, 3-5% on the C2R).  The C2R also stores its line-aligned
+// Workgroups are dealt to XCDs in contiguous ranges by the C2R at every N
+// (3-5%) and by the R2C from N = 1024 up (2-3%).  The C2R also stores its
+// line-aligned
 // real rows non-temporally (they are not read again soon); the R2C's
 // complex rows are not line-aligned and gain nothing from it.
 template <typename T, bool FWD, int N>
@@ -313,8 +317,7 @@ struct sshape {
 };
 
 // XP: LDS rounds per exchange.  1 = whole complex values, 2 = real then
-// imaginary parts, 2P (P > 1) = real and imaginary parts of P position
-// ranges; the LDS tile is N*TC/XP complex values.
+// imaginary parts; the LDS tile is N*TC/XP complex values (padded).
 // NT: non-temporal loads and stores of the lines (no reuse), for tilings in
 // which every 128-byte line belongs to one tile (the host checks this).
 template <typename T, int N, int TC, int XP, int S, int E = 16, int MF = 0, bool NT = false>
@@ -323,8 +326,8 @@ __global__ __launch_bounds__(TC * N / E) void k_strided(
     int64_t tiles_m, line_map lm) {
     constexpr int TPT = N / E;
     constexpr bool SPLIT = XP == 2;
-    static_assert(XP == 1 || XP % 2 == 0, "XP must be 1 or even");
-    constexpr int PS = XP > 2 ? 0 : first_radix_shift<E>::value;
+    static_assert(XP == 1 || XP == 2, "XP: whole values (1) or real/imaginary halves (2)");
+    constexpr int PS = first_radix_shift<E>::value;
     constexpr int NP = padded_len<N, PS>::value;
     __shared__ cx<T> lds[(NP * TC + XP - 1) / XP];
     using IX = idx_cols<TC, PS>;
@@ -372,16 +375,12 @@ __global__ __launch_bounds__(TC * N / E) void k_strided(
                 a[i] = *p;
             }
         }
-        if constexpr (XP > 2)
-            fft_regs<T, N, E, S>(a, t, tw, 1,
-                                 xch_parts<T, IX, XP / 2>{reinterpret_cast<T*>(lds), IX{c}});
-        else if constexpr (SPLIT)
+        if constexpr (SPLIT)
             fft_regs<T, N, E, S>(a, t, tw, 1,
                                  xch_split<T, IX>{reinterpret_cast<T*>(lds), IX{c}});
         else
             fft_regs<T, N, E, S>(a, t, tw, 1, xch_full<T, IX>{lds, IX{c}});
     } else {
-        static_assert(XP <= 2, "MFMA stage: whole or re/im exchange");
         // First radix-16 stage on the matrix cores.  The wave's 64 butterflies
         // (those of its own threads, j = t for thread (c, t)) go in two groups
         // of 32; lane (h, n) loads inputs 8h..8h+7 of butterfly 32g + n.

@@ -220,6 +220,54 @@ def variants(n: int, steps: int, x64: torch.Tensor, dev) -> dict:
     del G, h, p64
     torch.cuda.empty_cache()
     out.update(pencil_variants(steps, dev))
+    out.update(graph_variants(steps, dev))
+    return out
+
+
+def graph_variants(steps: int, dev) -> dict:
+    """Small transforms whose kernels last tens of microseconds, eager and as
+    one replayed HIP graph (the exec calls only enqueue kernels, so a
+    forward + inverse pair captures as is): 8 x 256^3 FP32 round trip, and
+    the local forward chain of a 64 x 128 pencil share of 4096^3 FP64."""
+    import synth
+    from paper_2202_12756_amd import PencilPlan, Plan
+
+    def capture(fn):
+        s = torch.cuda.Stream(dev)
+        s.wait_stream(torch.cuda.current_stream(dev))
+        with torch.cuda.stream(s):
+            fn()
+        torch.cuda.current_stream(dev).wait_stream(s)
+        torch.cuda.synchronize()
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g):
+            fn()
+        return g
+
+    out = {}
+    n = 256
+    p = Plan(n, torch.float32, batch=8, device=dev)
+    x = synth.uniform(p.real_shape, 5, torch.float32, dev)
+    F, y = p.empty_spectrum(), p.empty_real()
+    pair = lambda: (p.r2c(x, F), p.c2r(F, y, 1.0 / n ** 3))
+    eager = time_pairs(pair, steps, 2)
+    g = capture(pair)
+    graph = time_pairs(g.replay, steps, 2)
+    out["graph_8x256_f32_pair"] = {"eager_ms": round(eager, 4), "graph_ms": round(graph, 4)}
+    del p, x, F, y, g
+    pp = PencilPlan(4096, torch.float64, (64, 128), 0, device=dev)
+    xr = synth.uniform(pp.real_shape, 11, torch.float64, dev)
+    send = torch.empty(pp.send_shape, dtype=torch.complex128, device=dev)
+    yp = torch.view_as_complex(synth.uniform(pp.ypencil_shape + (2,), 12, torch.float64, dev))
+    xp = torch.view_as_complex(synth.uniform(pp.xpencil_shape + (2,), 13, torch.float64, dev))
+    chain = lambda: (pp.z_r2c(xr, send), pp.y_c2c(yp, -1), pp.x_c2c(xp, -1))
+    eager = time_pairs(chain, steps, 2)
+    g = capture(chain)
+    graph = time_pairs(g.replay, steps, 2)
+    out["graph_pencil_4096_64x128_f64_chain"] = {"eager_ms": round(eager, 4),
+                                                 "graph_ms": round(graph, 4)}
+    del pp, xr, send, yp, xp, g
+    torch.cuda.empty_cache()
     return out
 
 

@@ -572,11 +572,13 @@ static hipError_t strided_ax(int sign, void* data, const void* tw, int64_t m_col
     if (blocks == 0) return hipSuccess;
     if (blocks > kMaxBlocks) return hipErrorInvalidValue;
     const dim3 threads(TC * SH::TPT);
-    // x lines of large grids stream through non-temporally when every tile
-    // owns whole 128-byte lines: 2% faster in FP64, 4% in FP32 at 1024^3.
-    // (Where neighbouring tiles share lines, as in the y passes, the hint
-    // makes the shared lines travel twice and costs 15-30%.)
-    if constexpr (AX == 1 && MF == 0 && N >= 512 && (TC * sizeof(cx<T>)) % 128 == 0) {
+    // x lines of N = 512 and 1024 stream through non-temporally when every
+    // tile owns whole 128-byte lines: 2% faster in FP64, 4% in FP32 at
+    // 1024^3, where two workgroups share a CU.  At N = 2048 (one 512-thread
+    // workgroup per CU) the hint cost FP64 5%; where neighbouring tiles share
+    // lines, as in the y passes, it makes them travel twice (15-30% slower).
+    if constexpr (AX == 1 && MF == 0 && N >= 512 && N <= 1024 &&
+                  (TC * sizeof(cx<T>)) % 128 == 0) {
         if (whole_lines(data, m_cols, lm, 128 / int64_t(sizeof(cx<T>)))) {
             if (sign < 0)
                 hipLaunchKernelGGL((k_strided<T, N, TC, SH::XP, -1, SH::E, 0, true>), dim3(blocks),

@@ -102,8 +102,10 @@ typedef struct {
      * slab_x = X = N/pr, ranks = pr * pc, real_bytes = batch * X * Y * N
      * reals, complex_bytes = batch * X * Y * K complex (first-exchange
      * order), pencil_bytes = batch * pc * X * Y * w complex (the y- and
-     * x-pencils), chunk_bytes = X * Y * w complex (one block of either
-     * exchange per source rank, per grid).  Slab plans report grid_r = p,
+     * x-pencils and the pr > pc send order), chunk_bytes = X * Y * w
+     * complex (one first-exchange block per source rank, per grid; a
+     * second-exchange block is pencil_bytes / (batch pr)).  Slab plans
+     * report grid_r = p,
      * grid_c = 1, col = 0, y_local = N, kz_width = K. */
     int64_t grid_r;        /* pr: process-grid rows (x is cut pr ways)     */
     int64_t grid_c;        /* pc: process-grid columns (y, then kz)        */
@@ -135,7 +137,7 @@ gfft_status gfft_plan_create(gfft_plan **out, int64_t n, gfft_dtype dtype,
 /*
  * Create a plan for one GPU's share of a pencil-decomposed N^3 real grid
  * (section 2, pencil decomposition: p = pr x pc processors, each holding
- * (N/pr) x (N/pc) x N real values; up to N^2/4 processors here, so p may
+ * (N/pr) x (N/pc) x N real values; up to N^2/2 processors here, so p may
  * exceed N, the slab limit).  Rank (r, c) owns x in [r X, (r+1) X) and y in
  * [c Y, (c+1) Y), X = N/pr, Y = N/pc, all z.  The forward transform is
  *   1. gfft_exec_z_r2c: rows [batch][X][Y][N] -> half-spectrum rows written
@@ -148,26 +150,32 @@ gfft_status gfft_plan_create(gfft_plan **out, int64_t n, gfft_dtype dtype,
  *      [pc][X][Y][w] (w = w_c): element (c', x_l, y_l, kz_l) is
  *      (x = r X + x_l, y = c' Y + y_l, kz = c w0 + kz_l).
  *   3. gfft_exec_y_c2c: in place along y on that y-pencil.
- *   4. exchange 2 (caller, among the pr ranks of column c): with g = pc/pr,
- *      blocks c' in [r' g, (r'+1) g) of the y-pencil -- one contiguous run
- *      of g X Y w values -- go to rank (r', c), which stores the run from
- *      rank (r, c) as block r of its x-pencil [pr][g][X][Y][w]: element
- *      (r, g_l, x_l, y_l, kz_l) is (x = r X + x_l, y = r' N/pr + g_l Y +
- *      y_l, kz = c w0 + kz_l).
+ *   4. exchange 2 (caller, among the pr ranks of column c).  pr <= pc: with
+ *      g = pc/pr, blocks c' in [r' g, (r'+1) g) of the y-pencil -- one
+ *      contiguous run of g X Y w values -- go to rank (r', c), which stores
+ *      the run from rank (r, c) as block r of its x-pencil
+ *      [pr][g][X][Y][w]: element (r, g_l, x_l, y_l, kz_l) is (x = r X + x_l,
+ *      y = r' N/pr + g_l Y + y_l, kz = c w0 + kz_l).  pr > pc: with
+ *      h = pr/pc, gfft_pack_slab_for_alltoall first splits every y-pencil
+ *      block into h runs [X][N/pr][w] (send order [pc][h][X][N/pr][w]);
+ *      run (c', s) goes to rank (c' h + s, c), which stores the run from
+ *      rank (r, c) as block r of its x-pencil [pr][X][N/pr][w] = [N][N/pr][w]
+ *      (x = r X + x_l, y = r' N/pr + y_l, kz = c w0 + kz_l).
  *   5. gfft_exec_x_c2c: in place along x on that x-pencil.
  * The inverse runs 5, 4, 3, 2, 1 backwards (gfft_exec_x_c2c and
  * gfft_exec_y_c2c with sign +1, the exchanges returning every block to its
- * sender, gfft_exec_z_c2r reading the first-exchange order).  Each exchange
- * is per grid of the batch.
- *   grid_r, grid_c : pr, pc, powers of two with pr <= pc <= N/2.
+ * sender, gfft_unpack_slab_from_alltoall undoing the pack when pr > pc,
+ * gfft_exec_z_c2r reading the first-exchange order).  Each exchange is per
+ * grid of the batch.
+ *   grid_r, grid_c : pr, pc, powers of two with pr <= N, pc <= N/2.
  *   col            : this rank's c (it fixes w: w0, or w0 + 1 when
  *                    c = pc - 1).
  *   flags          : 0 or one of GFFT_MFMA_BF16X2 / GFFT_MFMA_BF16X3 (FP32,
  *                    N >= 32); the slab flags return GFFT_E_UNSUPPORTED.
- * gfft_exec_r2c / c2r / the adjoints and the slab pack/unpack return
- * GFFT_E_UNSUPPORTED on pencil plans (their local work is steps 1 and 5
- * apart); gfft_exec_z_r2c's scale/weighted arguments give the adjoint's
- * bin factors as for slabs.
+ * gfft_exec_r2c / c2r and the adjoints return GFFT_E_UNSUPPORTED on pencil
+ * plans (their local work is steps 1 and 5 apart), and so do the pack and
+ * unpack when pr <= pc (no pack is needed); gfft_exec_z_r2c's
+ * scale/weighted arguments give the adjoint's bin factors as for slabs.
  */
 gfft_status gfft_pencil_plan_create(gfft_plan **out, int64_t n,
                                     gfft_dtype dtype, int64_t grid_r,

@@ -313,20 +313,48 @@ def pencil_y_c2c(ypencil: np.ndarray, sign: int, method=None) -> np.ndarray:
 
 def pencil_exchange2(ypencils: list[np.ndarray], pr: int) -> list[np.ndarray]:
     """Exchange 2 inside one grid column: ``ypencils[r]`` is rank (r, c)'s
-    y-pencil [..., pc, X, Y, w]; rank (r', c) receives blocks [r' g,
-    (r'+1) g) (g = pc/pr) of every rank r as block r of its x-pencil
-    [..., pr, g, X, Y, w]."""
+    y-pencil [..., pc, X, Y, w].  pr <= pc: rank (r', c) receives blocks
+    [r' g, (r'+1) g) (g = pc/pr) of every rank r as block r of its x-pencil
+    [..., pr, g, X, Y, w].  pr > pc (h = pr/pc): rank r' = c' h + s receives
+    rows [s N/pr, (s+1) N/pr) of block c' of every rank r as block r of its
+    x-pencil [..., pr, X, N/pr, w]."""
     pc = ypencils[0].shape[-4]
-    g = pc // pr
-    return [np.stack([yp[..., rp * g:(rp + 1) * g, :, :, :] for yp in ypencils], axis=-5)
+    if pr <= pc:
+        g = pc // pr
+        return [np.stack([yp[..., rp * g:(rp + 1) * g, :, :, :] for yp in ypencils], axis=-5)
+                for rp in range(pr)]
+    h = pr // pc
+    yr = ypencils[0].shape[-2] // h
+    return [np.stack([yp[..., rp // h, :, (rp % h) * yr:(rp % h + 1) * yr, :] for yp in ypencils],
+                     axis=-4)
             for rp in range(pr)]
 
 
-def pencil_exchange2_back(xpencils: list[np.ndarray]) -> list[np.ndarray]:
-    """Inverse of :func:`pencil_exchange2`."""
+def pencil_exchange2_back(xpencils: list[np.ndarray], pc: int) -> list[np.ndarray]:
+    """Inverse of :func:`pencil_exchange2` (``pc`` columns in the grid)."""
     pr = len(xpencils)
-    return [np.concatenate([xpencils[rp][..., r, :, :, :, :] for rp in range(pr)], axis=-4)
-            for r in range(pr)]
+    if pr <= pc:
+        return [np.concatenate([xpencils[rp][..., r, :, :, :, :] for rp in range(pr)], axis=-4)
+                for r in range(pr)]
+    h = pr // pc
+    out = []
+    for r in range(pr):
+        blocks = [np.concatenate([xpencils[cp * h + s][..., r, :, :, :] for s in range(h)],
+                                 axis=-2)
+                  for cp in range(pc)]
+        out.append(np.stack(blocks, axis=-4))
+    return out
+
+
+def pencil_pack2(ypencil: np.ndarray, h: int) -> np.ndarray:
+    """Second-exchange send order of a pr > pc rank (h = pr/pc): run (c', s)
+    = rows [s Y/h, (s+1) Y/h) of y-pencil block c', for peer c' h + s:
+    [..., pc, X, Y, w] -> [..., pc, h, X, Y/h, w]."""
+    *lead, pc, x, y, w = ypencil.shape
+    nl = len(lead)
+    t = ypencil.reshape(*lead, pc, x, h, y // h, w)
+    perm = list(range(nl)) + [nl, nl + 2, nl + 1, nl + 3, nl + 4]
+    return np.ascontiguousarray(t.transpose(perm))
 
 
 def pencil_x_c2c(xpencil: np.ndarray, sign: int, method=None) -> np.ndarray:

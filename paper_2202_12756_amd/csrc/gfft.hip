@@ -22,10 +22,12 @@ struct gfft_plan {
     // z rows per grid: X * N (slab), X * Y (pencil: x and y extents local)
     int64_t zrows;
     // pencil plans: pr x pc process grid, this rank's column `col`, its kz
-    // width w = N/(2 pc) (+1 for the last column), g = pc / pr
+    // width w = N/(2 pc) (+1 for the last column); g = pc/pr y-pencil blocks
+    // per second-exchange peer (pr <= pc), or h = pr/pc peers per y-pencil
+    // block (pr > pc, the block then packed into h runs of N/pr rows)
     bool pencil;
-    int64_t pr, pc, col, w, g;
-    int lg_w0, lg_g;
+    int64_t pr, pc, col, w, g, h;
+    int lg_w0, lg_g, lg_h;
 };
 
 namespace {
@@ -147,6 +149,15 @@ gfft::line_map ymap(const gfft_plan* p) {
 // step 4 folded into the addressing (a batch of Y line sets, K columns each).
 gfft::line_map xmap(const gfft_plan* p) {
     gfft::line_map lm;
+    if (p->pencil && p->h > 1) {  // [batch][pr][X][N/pr][w] = [batch][N][N/pr][w]
+        lm.b_hi = p->n * (p->n / p->pr) * p->w;
+        lm.b_lo = 0;
+        lm.s_hi = 0;
+        lm.s_lo = (p->n / p->pr) * p->w;
+        lm.lg_bx = 0;
+        lm.lg_y = p->lg_n;
+        return lm;
+    }
     if (p->pencil) {  // [batch][pr][g][X][Y][w]: x = r X + x_l, line sets (item, g_l)
         lm.b_hi = p->pc * p->x * p->y * p->w;
         lm.lg_bx = p->lg_g;
@@ -207,8 +218,12 @@ gfft_status run_y(const gfft_plan* p, void* data, int sign, hipStream_t s) {
 }
 
 gfft_status run_x(const gfft_plan* p, void* data, int sign, hipStream_t s) {
-    const int64_t cols = p->pencil ? p->y * p->w : paper(p) ? p->k : p->y * p->k;
-    const int64_t sets = p->pencil ? p->batch * p->g : paper(p) ? p->batch * p->y : p->batch;
+    int64_t cols = paper(p) ? p->k : p->y * p->k;
+    int64_t sets = paper(p) ? p->batch * p->y : p->batch;
+    if (p->pencil) {
+        cols = p->h > 1 ? (p->n / p->pr) * p->w : p->y * p->w;
+        sets = p->h > 1 ? p->batch : p->batch * p->g;
+    }
     return hip_status(gfft::launch_strided(f64(p), int(p->n), 1, mfma_terms(p), sign, data,
                                            p->tw, cols, sets, xmap(p), s));
 }
@@ -248,6 +263,21 @@ gfft_status inverse(const gfft_plan* p, void* in, void* out, double scale, bool 
     if (p->p == 1 && (st = run_x(p, in, +1, s)) != GFFT_OK) return st;
     if ((st = run_y(p, in, +1, s)) != GFFT_OK) return st;
     return run_z_c2r(p, in, out, scale, weighted, s);
+}
+
+// Second-exchange pack of a pencil plan with pr > pc: every y-pencil block
+// [X][Y][w] (per grid and c') splits into h = pr/pc runs [X][N/pr][w], run s
+// for peer c' h + s -- the slab pack's permutation with Y rows in h chunks.
+gfft_status pencil_pack(const gfft_plan* p, const void* src, void* dst, bool to_send,
+                        void* stream) {
+    if (p->h == 1) return GFFT_E_UNSUPPORTED;  // blocks already contiguous
+    gfft_status st = check_ptr(src);
+    if (st != GFFT_OK || (st = check_ptr(dst)) != GFFT_OK) return st;
+    const int64_t bytes = p->batch * p->pc * p->x * p->y * p->w * 2 * elt(p);
+    if (overlap(src, bytes, dst, bytes)) return GFFT_E_INVALID_ARG;
+    return hip_status(gfft::launch_pack(f64(p), src, dst, p->batch * p->pc * p->h * p->x,
+                                        p->lg_x, p->lg_h, p->y, p->y / p->h, p->w, to_send,
+                                        as_stream(stream)));
 }
 
 // The current device, if it is a gfx950.
@@ -357,8 +387,10 @@ gfft_status gfft_plan_create(gfft_plan** out, int64_t n, gfft_dtype dtype, int64
     p->col = 0;
     p->w = k;
     p->g = 1;
+    p->h = 1;
     p->lg_w0 = 0;
     p->lg_g = 0;
+    p->lg_h = 0;
     if ((st = upload_twiddles(p)) != GFFT_OK) {
         delete p;
         return st;
@@ -378,9 +410,8 @@ gfft_status gfft_pencil_plan_create(gfft_plan** out, int64_t n, gfft_dtype dtype
     if (col < 0 || col >= grid_c) return GFFT_E_INVALID_ARG;
     if (!pow2(n) || n < 16 || n > 4096) return GFFT_E_UNSUPPORTED;
     if (!pow2(grid_r) || !pow2(grid_c)) return GFFT_E_INVALID_ARG;
-    // kz is cut into grid_c chunks of N/(2 grid_c) bins; the second exchange
-    // moves whole first-exchange blocks only when grid_r <= grid_c.
-    if (grid_c > n / 2 || grid_r > grid_c) return GFFT_E_UNSUPPORTED;
+    // kz is cut into grid_c chunks of N/(2 grid_c) bins; x into grid_r slabs
+    if (grid_c > n / 2 || grid_r > n) return GFFT_E_UNSUPPORTED;
     const uint32_t mf = flags & (GFFT_MFMA_BF16X2 | GFFT_MFMA_BF16X3);
     if (mf == (GFFT_MFMA_BF16X2 | GFFT_MFMA_BF16X3)) return GFFT_E_INVALID_ARG;
     if (mf && (dtype != GFFT_F32 || n < 32)) return GFFT_E_UNSUPPORTED;
@@ -420,9 +451,11 @@ gfft_status gfft_pencil_plan_create(gfft_plan** out, int64_t n, gfft_dtype dtype
     p->pc = grid_c;
     p->col = col;
     p->w = w;
-    p->g = grid_c / grid_r;
+    p->g = grid_r <= grid_c ? grid_c / grid_r : 1;
+    p->h = grid_r > grid_c ? grid_r / grid_c : 1;
     p->lg_w0 = ilog2(n / (2 * grid_c));
     p->lg_g = ilog2(p->g);
+    p->lg_h = ilog2(p->h);
     if ((st = upload_twiddles(p)) != GFFT_OK) {
         delete p;
         return st;
@@ -485,7 +518,7 @@ gfft_status gfft_exec_r2c_adjoint(const gfft_plan* p, void* in, void* out, doubl
 gfft_status gfft_pack_slab_for_alltoall(const gfft_plan* p, const void* src, void* dst,
                                         void* stream) {
     if (!p) return GFFT_E_INVALID_ARG;
-    if (p->pencil) return GFFT_E_UNSUPPORTED;
+    if (p->pencil) return pencil_pack(p, src, dst, true, stream);
     gfft_status st = check_ptr(src);
     if (st != GFFT_OK || (st = check_ptr(dst)) != GFFT_OK) return st;
     if (overlap(src, cplx_bytes(p), dst, cplx_bytes(p))) return GFFT_E_INVALID_ARG;
@@ -499,7 +532,7 @@ gfft_status gfft_pack_slab_for_alltoall(const gfft_plan* p, const void* src, voi
 gfft_status gfft_unpack_slab_from_alltoall(const gfft_plan* p, const void* src, void* dst,
                                            void* stream) {
     if (!p) return GFFT_E_INVALID_ARG;
-    if (p->pencil) return GFFT_E_UNSUPPORTED;
+    if (p->pencil) return pencil_pack(p, src, dst, false, stream);
     gfft_status st = check_ptr(src);
     if (st != GFFT_OK || (st = check_ptr(dst)) != GFFT_OK) return st;
     if (overlap(src, cplx_bytes(p), dst, cplx_bytes(p))) return GFFT_E_INVALID_ARG;

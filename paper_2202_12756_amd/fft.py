@@ -282,9 +282,12 @@ class PencilPlan:
     [batch, X*Y*K]: chunk c' = kz in ``kz_range(c')``, a [X, Y, w_c'] block
     (``chunk`` gives views).  After exchange 1 the y pass runs on the
     y-pencil [batch, pc, X, Y, w] (block c' from rank (r, c')); after
-    exchange 2 the x pass runs on the x-pencil [batch, pr, g, X, Y, w]
-    (g = pc/pr; block r from rank (r, c) = its y-pencil blocks
-    [r' g, (r'+1) g) for destination r').  Requires pr <= pc <= N/2.
+    exchange 2 the x pass runs on the x-pencil: for pr <= pc
+    [batch, pr, g, X, Y, w] (g = pc/pr; block r from rank (r, c) = its
+    y-pencil blocks [r' g, (r'+1) g) for destination r'); for pr > pc
+    [batch, pr, X, N/pr, w] (block r = run (c', s), r' = c' h + s, of rank
+    (r, c)'s packed y-pencil ``pack2`` [batch, pc, h, X, N/pr, w]).
+    Requires pc <= N/2.
     """
 
     _check = Plan._check
@@ -316,7 +319,8 @@ class PencilPlan:
         self.y = s.y_local
         self.w = s.kz_width
         self.w0 = self.n // (2 * self.pc)
-        self.g = self.pc // self.pr
+        self.g = max(self.pc // self.pr, 1)
+        self.h = max(self.pr // self.pc, 1)
 
     def kz_range(self, c: int):
         """The kz bins [k0, k1) that column c holds after exchange 1."""
@@ -337,7 +341,35 @@ class PencilPlan:
 
     @property
     def xpencil_shape(self):
+        if self.h > 1:
+            return (self.batch, self.pr, self.x, self.n // self.pr, self.w)
         return (self.batch, self.pr, self.g, self.x, self.y, self.w)
+
+    @property
+    def send2_shape(self):
+        """Second-exchange send order of a pr > pc plan (run (c', s) for
+        peer c' h + s)."""
+        return (self.batch, self.pc, self.h, self.x, self.n // self.pr, self.w)
+
+    def pack2(self, ypencil, out=None):
+        """Split each y-pencil block into h runs for exchange 2 (pr > pc)."""
+        out = (torch.empty(self.send2_shape, dtype=self.cdtype, device=self.device)
+               if out is None else out)
+        a = self._check(ypencil, self.cdtype, self._n(self.ypencil_shape), "y-pencil")
+        b = self._check(out, self.cdtype, self._n(self.send2_shape), "send")
+        _lib.check(_lib.gfft_pack_slab_for_alltoall(self._h, a, b, _stream(self.device)),
+                   "gfft_pack_slab_for_alltoall")
+        return out
+
+    def unpack2(self, send, out=None):
+        """Inverse of ``pack2``."""
+        out = (torch.empty(self.ypencil_shape, dtype=self.cdtype, device=self.device)
+               if out is None else out)
+        a = self._check(send, self.cdtype, self._n(self.send2_shape), "send")
+        b = self._check(out, self.cdtype, self._n(self.ypencil_shape), "y-pencil")
+        _lib.check(_lib.gfft_unpack_slab_from_alltoall(self._h, a, b, _stream(self.device)),
+                   "gfft_unpack_slab_from_alltoall")
+        return out
 
     def chunk(self, send: torch.Tensor, c: int) -> torch.Tensor:
         """View [batch, X, Y, w_c] of chunk c of a first-exchange buffer."""

@@ -80,7 +80,9 @@ def test_plan_create_validates_on_host(args, expect):
     ((64, 0, 2, 4, 1, 1, 0), None),                            # valid
     ((64, 0, 8, 16, 15, 1, 0), None),                          # p = 128 > N
     ((64, 0, 1, 1, 0, 1, 0), None),                            # one rank
-    ((64, 0, 4, 2, 0, 1, 0), _lib.GFFT_E_UNSUPPORTED),         # pr > pc
+    ((64, 0, 4, 2, 0, 1, 0), None),                            # pr > pc (packed exchange 2)
+    ((64, 0, 64, 32, 0, 1, 0), None),                          # p = N^2/2
+    ((16, 0, 32, 4, 0, 1, 0), _lib.GFFT_E_UNSUPPORTED),        # pr > N
     ((64, 0, 2, 64, 0, 1, 0), _lib.GFFT_E_UNSUPPORTED),        # pc > N/2
     ((64, 0, 3, 4, 0, 1, 0), _lib.GFFT_E_INVALID_ARG),         # pr not 2^m
     ((64, 0, 2, 4, 4, 1, 0), _lib.GFFT_E_INVALID_ARG),         # col >= pc

@@ -7,12 +7,13 @@ import pytest
 import torch
 
 import oracle
-from helpers import TOL, host, real_input, rel_l2
+from helpers import TOL, cplx_input, host, real_input, rel_l2
 from paper_2202_12756_amd import GfftError, PencilPlan, _lib
 
 pytestmark = pytest.mark.gpu
 
-CASES = [(16, 2, 4), (32, 4, 8), (32, 8, 16), (64, 2, 2), (64, 4, 16), (128, 4, 4)]
+CASES = [(16, 2, 4), (32, 4, 8), (32, 8, 16), (64, 2, 2), (64, 4, 16), (128, 4, 4),
+         (32, 8, 2), (32, 32, 16), (128, 16, 4)]
 
 
 def _plans(n, pr, pc, dtype, batch=1, mfma_terms=0):
@@ -35,7 +36,8 @@ def test_pencil_matrix_core_stage():
 def _pipeline(n, pr, pc, dtype, mfma):
     f, fref = real_input((n, n, n), 1200 + n + pr + pc, dtype)
     plans = _plans(n, pr, pc, dtype, mfma_terms=mfma)
-    x, y, g = n // pr, n // pc, pc // pr
+    x, y = n // pr, n // pc
+    g, h = max(pc // pr, 1), max(pr // pc, 1)
     F = oracle.r2c3d(fref)
     # step 1: z R2C into first-exchange order, per rank
     sends = {}
@@ -59,20 +61,31 @@ def _pipeline(n, pr, pc, dtype, mfma):
         [oracle.pencil_send(oracle.r2c_last(fref[:x, c * y:(c + 1) * y]), pc) for c in range(pc)],
         x, y)[pc - 1], -1)
     assert rel_l2(host(ypen[0, pc - 1])[0], yref) <= TOL[dtype]
-    # exchange 2 and the x pass
-    xpen = {}
+    # exchange 2 (through the pack when pr > pc) and the x pass
+    xpen, send2 = {}, {}
+    if h > 1:
+        for key in ypen:
+            send2[key] = plans[key[1]].pack2(ypen[key])
     for c in range(pc):
         for rp in range(pr):
             xp = torch.empty(plans[c].xpencil_shape, dtype=plans[c].cdtype, device="cuda")
             for r in range(pr):
-                xp[:, r].copy_(ypen[r, c][:, rp * g:(rp + 1) * g])
+                if h > 1:
+                    xp[:, r].copy_(send2[r, c][:, rp // h, rp % h])
+                else:
+                    xp[:, r].copy_(ypen[r, c][:, rp * g:(rp + 1) * g])
             xpen[rp, c] = plans[c].x_c2c(xp, -1)
     torch.cuda.synchronize()
     for (rp, c), got in xpen.items():
         k0, k1 = oracle.pencil_kz_range(n, pc, c)
-        r_, g_, x_, y_, k_ = np.meshgrid(np.arange(pr), np.arange(g), np.arange(x),
-                                         np.arange(y), np.arange(k1 - k0), indexing="ij")
-        want = F[r_ * x + x_, rp * (n // pr) + g_ * y + y_, k0 + k_]
+        if h > 1:
+            r_, x_, y_, k_ = np.meshgrid(np.arange(pr), np.arange(x), np.arange(n // pr),
+                                         np.arange(k1 - k0), indexing="ij")
+            want = F[r_ * x + x_, rp * (n // pr) + y_, k0 + k_]
+        else:
+            r_, g_, x_, y_, k_ = np.meshgrid(np.arange(pr), np.arange(g), np.arange(x),
+                                             np.arange(y), np.arange(k1 - k0), indexing="ij")
+            want = F[r_ * x + x_, rp * (n // pr) + g_ * y + y_, k0 + k_]
         assert rel_l2(host(got)[0], want) <= TOL[dtype], (rp, c)
     # inverse: x^-1, exchange 2 back, y^-1, exchange 1 back, z C2R
     for key in xpen:
@@ -80,7 +93,12 @@ def _pipeline(n, pr, pc, dtype, mfma):
     for c in range(pc):
         for r in range(pr):
             for rp in range(pr):
-                ypen[r, c][:, rp * g:(rp + 1) * g].copy_(xpen[rp, c][:, r])
+                if h > 1:
+                    send2[r, c][:, rp // h, rp % h].copy_(xpen[rp, c][:, r])
+                else:
+                    ypen[r, c][:, rp * g:(rp + 1) * g].copy_(xpen[rp, c][:, r])
+            if h > 1:
+                plans[c].unpack2(send2[r, c], ypen[r, c])
             plans[c].y_c2c(ypen[r, c], +1)
     out = torch.empty_like(f)
     for r in range(pr):
@@ -124,7 +142,24 @@ def test_pencil_plan_rejects_slab_entry_points():
     assert sz["kz_width"] == 4 and sz["y_local"] == 8 and sz["slab_x"] == 16
     assert sz["pencil_bytes"] == 4 * 16 * 8 * 4 * 16
     with pytest.raises(GfftError):
-        PencilPlan(32, torch.float64, (8, 4), 0)
+        PencilPlan(32, torch.float64, (4, 32), 0)         # pc > N/2
+    yp = torch.zeros(p.ypencil_shape, dtype=torch.complex128, device="cuda")
+    assert (_lib.gfft_pack_slab_for_alltoall(p._h, yp.data_ptr(), b.data_ptr(), s)
+            == _lib.GFFT_E_UNSUPPORTED)                   # pr <= pc: nothing to pack
+
+
+def test_pencil_pack2_bit_exact():
+    """pr > pc: the second-exchange pack is the oracle's permutation, and
+    unpack inverts it, bit for bit."""
+    n, pr, pc = 64, 8, 2
+    for dtype in (torch.float64, torch.float32):
+        p = PencilPlan(n, dtype, (pr, pc), 1, batch=2)
+        yp, ypref = cplx_input(p.ypencil_shape, 1330, dtype)
+        send = p.pack2(yp)
+        back = p.unpack2(send)
+        torch.cuda.synchronize()
+        assert np.array_equal(host(send), oracle.pencil_pack2(host(yp), p.h))
+        assert torch.equal(back, yp)
 
 
 @pytest.mark.parametrize("col", [0, 31])

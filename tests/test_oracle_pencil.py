@@ -8,7 +8,8 @@ import pytest
 import oracle
 import synth
 
-CASES = [(16, 1, 1), (16, 1, 2), (16, 2, 2), (16, 2, 4), (16, 4, 8), (32, 2, 8), (32, 8, 16)]
+CASES = [(16, 1, 1), (16, 1, 2), (16, 2, 2), (16, 2, 4), (16, 4, 8), (32, 2, 8), (32, 8, 16),
+         (16, 4, 2), (16, 16, 8), (32, 32, 16)]
 
 
 def test_kz_ranges_partition_the_half_spectrum():
@@ -53,7 +54,10 @@ def _forward(f, n, pr, pc):
             ys[r, c] = oracle.pencil_y_c2c(yp, -1)
     for c in range(pc):
         for rp, xpen in enumerate(oracle.pencil_exchange2([ys[r, c] for r in range(pr)], pr)):
-            xp[rp, c] = oracle.pencil_x_c2c(xpen, -1)
+            if pr <= pc:
+                xp[rp, c] = oracle.pencil_x_c2c(xpen, -1)
+            else:                              # [pr][X][N/pr][w] = [N][N/pr][w]
+                xp[rp, c] = oracle.x_c2c(xpen.reshape(n, n // pr, -1), -1).reshape(xpen.shape)
     return xp, ys
 
 
@@ -64,14 +68,21 @@ def test_pencil_pipeline_equals_full_transform(n, pr, pc):
     in the last cases."""
     f = synth.uniform((n, n, n), 900 + n + pr + pc, torch.float64, "cpu").numpy()
     F = oracle.r2c3d(f)
-    x, y, g, w0 = n // pr, n // pc, pc // pr, n // (2 * pc)
+    x, y, w0 = n // pr, n // pc, n // (2 * pc)
     xp, _ = _forward(f, n, pr, pc)
     for (rp, c), got in xp.items():
         k0, k1 = oracle.pencil_kz_range(n, pc, c)
-        r_, g_, x_, y_, k_ = np.meshgrid(np.arange(pr), np.arange(g), np.arange(x), np.arange(y),
+        if pr <= pc:
+            g = pc // pr
+            r_, g_, x_, y_, k_ = np.meshgrid(np.arange(pr), np.arange(g), np.arange(x),
+                                             np.arange(y), np.arange(k1 - k0), indexing="ij")
+            want = F[r_ * x + x_, rp * (n // pr) + g_ * y + y_, c * w0 + k_]
+            assert got.shape == (pr, g, x, y, k1 - k0)
+        else:
+            r_, x_, y_, k_ = np.meshgrid(np.arange(pr), np.arange(x), np.arange(n // pr),
                                          np.arange(k1 - k0), indexing="ij")
-        want = F[r_ * x + x_, rp * (n // pr) + g_ * y + y_, c * w0 + k_]
-        assert got.shape == (pr, g, x, y, k1 - k0)
+            want = F[r_ * x + x_, rp * (n // pr) + y_, c * w0 + k_]
+            assert got.shape == (pr, x, n // pr, k1 - k0)
         assert np.max(np.abs(got - want)) <= 1e-12 * np.max(np.abs(F))
 
 
@@ -84,8 +95,14 @@ def test_pencil_round_trip(n, pr, pc):
     xp, _ = _forward(f, n, pr, pc)
     out = np.empty_like(f)
     for c in range(pc):
-        back = oracle.pencil_exchange2_back([oracle.pencil_x_c2c(xp[rp, c], +1)
-                                             for rp in range(pr)])
+        inv = []
+        for rp in range(pr):
+            if pr <= pc:
+                inv.append(oracle.pencil_x_c2c(xp[rp, c], +1))
+            else:
+                a = xp[rp, c]
+                inv.append(oracle.x_c2c(a.reshape(n, n // pr, -1), +1).reshape(a.shape))
+        back = oracle.pencil_exchange2_back(inv, pc)
         for r in range(pr):
             xp[r, c] = oracle.pencil_y_c2c(back[r], +1)          # reuse as y-pencils
     for r in range(pr):
@@ -104,6 +121,24 @@ def test_exchange_back_inverts_exchange():
     ys = oracle.pencil_exchange1(sends, x, y)
     for a, b in zip(oracle.pencil_exchange1_back(ys), sends):
         assert np.array_equal(a, b)
-    ypens = [rng.standard_normal((pc, x, y, 3)) for _ in range(pr)]
-    for a, b in zip(oracle.pencil_exchange2_back(oracle.pencil_exchange2(ypens, pr)), ypens):
-        assert np.array_equal(a, b)
+    for pr_ in (2, 8):           # pr <= pc and pr > pc
+        ypens = [rng.standard_normal((pc, x, y, 3)) for _ in range(pr_)]
+        back = oracle.pencil_exchange2_back(oracle.pencil_exchange2(ypens, pr_), pc)
+        for a, b in zip(back, ypens):
+            assert np.array_equal(a, b)
+
+
+def test_pack2_runs_are_the_second_exchange_blocks():
+    """pr > pc: run (c', s) of the packed y-pencil is exactly what
+    exchange 2 delivers to rank c' h + s."""
+    rng = np.random.default_rng(6)
+    pc, pr, x, y, w = 2, 8, 2, 8, 3
+    h = pr // pc
+    ypens = [rng.standard_normal((pc, x, y, w)) for _ in range(pr)]
+    recv = oracle.pencil_exchange2(ypens, pr)
+    for r, yp in enumerate(ypens):
+        packed = oracle.pencil_pack2(yp, h)
+        assert packed.shape == (pc, h, x, y // h, w)
+        for cp in range(pc):
+            for s in range(h):
+                assert np.array_equal(packed[cp, s], recv[cp * h + s][r])

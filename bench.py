@@ -307,26 +307,32 @@ def graph_variants(steps: int, dev) -> dict:
 def pencil_variants(steps: int, dev) -> dict:
     """One rank's local forward chain of a pencil-decomposed 4096^3 FP64 grid
     (z R2C into the first-exchange order, y pass on the received y-pencil,
-    x pass on the received x-pencil; the exchanges are the caller's), for
-    rank (0, 0) of a 16 x 32 grid (512 ranks, the paper's largest count) and
-    of a 64 x 128 grid (8192 ranks > N).  Bytes per pass: z reads the real
+    for pr > pc the second exchange's pack, x pass on the received x-pencil;
+    the exchanges are the caller's), for rank (0, 0) of a 16 x 32 grid (512
+    ranks, the paper's largest count), of a 64 x 128 grid (8192 ranks > N)
+    and of a 64 x 32 grid (pr > pc).  Bytes per pass: z reads the real
     pencil and writes the first-exchange buffer, y and x read and write their
     pencil in place."""
     import synth
     from paper_2202_12756_amd import PencilPlan
 
     n, out = 4096, {}
-    for pr, pc in ((16, 32), (64, 128)):
+    for pr, pc in ((16, 32), (64, 128), (64, 32)):
         p = PencilPlan(n, torch.float64, (pr, pc), 0, device=dev)
         xr = synth.uniform(p.real_shape, 11, torch.float64, dev)
         send = torch.empty(p.send_shape, dtype=torch.complex128, device=dev)
         yp = torch.view_as_complex(synth.uniform(p.ypencil_shape + (2,), 12, torch.float64, dev))
         xp = torch.view_as_complex(synth.uniform(p.xpencil_shape + (2,), 13, torch.float64, dev))
         ms = {"z_r2c": time_pairs(lambda: p.z_r2c(xr, send), steps, 2),
-              "y_fwd": time_pairs(lambda: p.y_c2c(yp, -1), steps, 2),
-              "x_fwd": time_pairs(lambda: p.x_c2c(xp, -1), steps, 2)}
-        bts = {"z_r2c": xr.numel() * 8 + send.numel() * 16,
-               "y_fwd": 2 * yp.numel() * 16, "x_fwd": 2 * xp.numel() * 16}
+              "y_fwd": time_pairs(lambda: p.y_c2c(yp, -1), steps, 2)}
+        bts = {"z_r2c": xr.numel() * 8 + send.numel() * 16, "y_fwd": 2 * yp.numel() * 16}
+        if p.h > 1:        # pr > pc: the second exchange's pack
+            send2 = torch.empty(p.send2_shape, dtype=torch.complex128, device=dev)
+            ms["pack2"] = time_pairs(lambda: p.pack2(yp, send2), steps, 2)
+            bts["pack2"] = 2 * yp.numel() * 16
+            del send2
+        ms["x_fwd"] = time_pairs(lambda: p.x_c2c(xp, -1), steps, 2)
+        bts["x_fwd"] = 2 * xp.numel() * 16
         total_ms = sum(ms.values())
         out[f"pencil_4096_{pr}x{pc}_f64"] = {
             "ranks": pr * pc, "real_pencil": f"{p.x}x{p.y}x{n}", "kz_width": p.w,

@@ -572,12 +572,13 @@ static hipError_t strided_ax(int sign, void* data, const void* tw, int64_t m_col
     if (blocks == 0) return hipSuccess;
     if (blocks > kMaxBlocks) return hipErrorInvalidValue;
     const dim3 threads(TC * SH::TPT);
-    // x lines of N = 512 and 1024 stream through non-temporally when every
-    // tile owns whole 128-byte lines: 2% faster in FP64, 4% in FP32 at
-    // 1024^3, where two workgroups share a CU.  At N = 2048 (one 512-thread
-    // workgroup per CU) the hint cost FP64 5%; where neighbouring tiles share
-    // lines, as in the y passes, it makes them travel twice (15-30% slower).
-    if constexpr (AX == 1 && MF == 0 && N >= 512 && N <= 1024 &&
+    // x lines stream through non-temporally when every tile owns whole
+    // 128-byte lines: at 1024^3 2% faster in FP64 and 4% in FP32, at 2048^3
+    // 8% faster in FP32 but 5% slower in FP64 (one 512-thread workgroup per
+    // CU), so FP64 uses it for N = 512 and 1024 only.  Where neighbouring
+    // tiles share lines, as in the y passes, the hint makes them travel twice
+    // (15-50% slower).
+    if constexpr (AX == 1 && MF == 0 && N >= 512 && (sizeof(T) == 4 || N <= 1024) &&
                   (TC * sizeof(cx<T>)) % 128 == 0) {
         if (whole_lines(data, m_cols, lm, 128 / int64_t(sizeof(cx<T>)))) {
             if (sign < 0)

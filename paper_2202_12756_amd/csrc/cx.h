@@ -136,6 +136,52 @@ __device__ __forceinline__ void dft16(cx<T>* a) {
     t = a[11]; a[11] = a[14]; a[14] = t;
 }
 
+// cos and sin of pi/16 and 3 pi/16 (nested half-angle formulas:
+// cos(pi/16) = sqrt(2 + sqrt(2 + sqrt 2)) / 2, and so on)
+template <typename T> struct k32_ {
+    static constexpr T c1 = T(0.98078528040323044912618223613423903697);
+    static constexpr T s1 = T(0.19509032201612826784828486847702224092);
+    static constexpr T c3 = T(0.83146961230254523707878837761790575673);
+    static constexpr T s3 = T(0.55557023301960222474283081394853287437);
+};
+
+// Radix 32 as 2 x 16 (decimation in time): with E and O the 16-point DFTs of
+// the even and odd inputs, y_k = E_k + w32^k O_k and y_(k+16) = E_k - w32^k O_k,
+// w32^k = cos(pi k/16) + S i sin(pi k/16).
+template <int S, typename T>
+__device__ __forceinline__ void dft32(cx<T>* a) {
+    cx<T> e[16], o[16];
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+        e[i] = a[2 * i];
+        o[i] = a[2 * i + 1];
+    }
+    dft16<S>(e);
+    dft16<S>(o);
+    const T c1 = k32_<T>::c1, s1 = k32_<T>::s1, c3 = k32_<T>::c3, s3 = k32_<T>::s3;
+    const T c2 = k_<T>::c8, s2 = k_<T>::s8;
+    o[1] = mul_cs<S>(o[1], c1, s1);
+    o[2] = mul_cs<S>(o[2], c2, s2);
+    o[3] = mul_cs<S>(o[3], c3, s3);
+    o[4] = mul_w8_1<S>(o[4]);
+    o[5] = mul_cs<S>(o[5], s3, c3);
+    o[6] = mul_cs<S>(o[6], s2, c2);
+    o[7] = mul_cs<S>(o[7], s1, c1);
+    o[8] = mul_si<S>(o[8]);
+    o[9] = mul_cs<S>(o[9], -s1, c1);
+    o[10] = mul_cs<S>(o[10], -s2, c2);
+    o[11] = mul_cs<S>(o[11], -s3, c3);
+    o[12] = mul_w8_3<S>(o[12]);
+    o[13] = mul_cs<S>(o[13], -c3, s3);
+    o[14] = mul_cs<S>(o[14], -c2, s2);
+    o[15] = mul_cs<S>(o[15], -c1, s1);
+#pragma unroll
+    for (int k = 0; k < 16; ++k) {
+        a[k] = e[k] + o[k];
+        a[k + 16] = e[k] - o[k];
+    }
+}
+
 template <int R, int S, typename T>
 __device__ __forceinline__ void dft(cx<T>* a) {
     if constexpr (R == 2) {
@@ -146,8 +192,10 @@ __device__ __forceinline__ void dft(cx<T>* a) {
         dft8<S>(a);
     } else if constexpr (R == 16) {
         dft16<S>(a);
+    } else if constexpr (R == 32) {
+        dft32<S>(a);
     } else {
-        static_assert(R == 1, "radix must be 1, 2, 4, 8 or 16");
+        static_assert(R == 1, "radix must be 1, 2, 4, 8, 16 or 32");
     }
 }
 

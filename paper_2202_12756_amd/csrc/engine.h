@@ -21,12 +21,12 @@
 
 namespace gfft {
 
-// Radix of the stage that starts at span L: min(E, 16) while the remaining
-// length allows, then whatever is left (N, E powers of two).  With E > 16 a
-// thread runs E/16 radix-16 butterflies per stage.
-template <int N, int E, int L>
+// Radix of the stage that starts at span L: min(E, RM) while the remaining
+// length allows, then whatever is left (N, E, RM powers of two; RM = 16 or
+// 32).  With E > RM a thread runs E/RM butterflies per stage.
+template <int N, int E, int L, int RM = 16>
 struct stage_radix {
-    static constexpr int RMAX = E < 16 ? E : 16;
+    static constexpr int RMAX = E < RM ? E : RM;
     static constexpr int value = (N / L) >= RMAX ? RMAX : (N / L);
 };
 
@@ -61,11 +61,12 @@ struct idx_rows {
     __device__ __forceinline__ int at(int padded) const { return off + padded; }
     __device__ __forceinline__ int operator()(int pos) const { return at(lds_pad<PS>(pos)); }
 };
-// log2 of the first radix for E elements per thread
-template <int E>
+// log2 of the first radix for E elements per thread (radix cap RM)
+template <int E, int RM = 16>
 struct first_radix_shift {
-    static constexpr int R0 = E < 16 ? E : 16;
-    static constexpr int value = R0 >= 16 ? 4 : R0 >= 8 ? 3 : R0 >= 4 ? 2 : R0 >= 2 ? 1 : 0;
+    static constexpr int R0 = E < RM ? E : RM;
+    static constexpr int value =
+        R0 >= 32 ? 5 : R0 >= 16 ? 4 : R0 >= 8 ? 3 : R0 >= 4 ? 2 : R0 >= 2 ? 1 : 0;
 };
 
 // Exchange after a stage: every output slot q + r*NB goes to position
@@ -153,11 +154,11 @@ struct xch_split {
 
 // Run the stages from span L to the end.  `tw` is a table of
 // W_Ntab^m (m = 0..Ntab-1) with Ntab = N * tws; entry idx*tws is W_N^idx.
-template <typename T, int N, int E, int S, int L, class X>
+template <typename T, int N, int E, int S, int L, int RM = 16, class X>
 __device__ __forceinline__ void fft_from(cx<T> (&a)[E], int t,
                                          const cx<T>* __restrict__ tw, int tws,
                                          const X& xch) {
-    constexpr int R = stage_radix<N, E, L>::value;
+    constexpr int R = stage_radix<N, E, L, RM>::value;
     constexpr int NB = E / R;       // butterflies per thread
     constexpr int TPT = N / E;      // threads per transform
     constexpr bool LAST = (L * R == N);
@@ -183,15 +184,15 @@ __device__ __forceinline__ void fft_from(cx<T> (&a)[E], int t,
     }
     if constexpr (!LAST) {
         xch.template run<N, E, L, R>(a, t);
-        fft_from<T, N, E, S, L * R>(a, t, tw, tws, xch);
+        fft_from<T, N, E, S, L * R, RM>(a, t, tw, tws, xch);
     }
 }
 
-template <typename T, int N, int E, int S, class X>
+template <typename T, int N, int E, int S, int RM = 16, class X>
 __device__ __forceinline__ void fft_regs(cx<T> (&a)[E], int t,
                                          const cx<T>* __restrict__ tw, int tws,
                                          const X& xch) {
-    fft_from<T, N, E, S, 1>(a, t, tw, tws, xch);
+    fft_from<T, N, E, S, 1, RM>(a, t, tw, tws, xch);
 }
 
 }  // namespace gfft

@@ -26,6 +26,12 @@ constexpr int kThreads = 256;
 
 constexpr int ilog2_c(int v) { return v <= 1 ? 0 : 1 + ilog2_c(v / 2); }
 
+// Largest radix per FFT stage.  The FP32 vector kernels take radix-32
+// stages, one LDS exchange fewer for 512- and 1024-point transforms (FP32 is
+// bound by instruction issue); FP64 and the matrix-core stage keep radix 16.
+template <typename T, int MF = 0>
+constexpr int radix_cap() { return sizeof(T) == 4 && MF == 0 ? 32 : 16; }
+
 // A workgroup-uniform value in scalar registers that the optimiser cannot
 // see through: expressions of it are formed where they are used.
 __device__ __forceinline__ int opaque_uniform(int v) {
@@ -110,7 +116,8 @@ __device__ __forceinline__ void z_r2c_body(
     constexpr int M = N / 2, K = M + 1;
     using Z = zshape<M, EMAX, THREADS>;
     constexpr int E = Z::E, TPT = Z::TPT, RPB = Z::RPB;
-    constexpr int PS = first_radix_shift<E>::value, MP = padded_len<M, PS>::value;
+    constexpr int RM = radix_cap<T>();
+    constexpr int PS = first_radix_shift<E, RM>::value, MP = padded_len<M, PS>::value;
     __shared__ cx<T> lds[RPB * MP];
 
     const int rl = threadIdx.x / TPT;
@@ -126,7 +133,7 @@ __device__ __forceinline__ void z_r2c_body(
     for (int m = 0; m < E; ++m) a[m] = src[t + m * TPT];
 
     const idx_rows<PS> ix{rl * MP};
-    fft_regs<T, M, E, -1>(a, t, tw, 2, xch_full<T, idx_rows<PS>>{lds, ix});
+    fft_regs<T, M, E, -1, RM>(a, t, tw, 2, xch_full<T, idx_rows<PS>>{lds, ix});
 
     // Split Z = FFT_M(z) into the real transform:
     //   X[k] = (Z[k] + conj Z[M-k])/2 - (i/2) W_N^k (Z[k] - conj Z[M-k]),
@@ -201,7 +208,8 @@ __device__ __forceinline__ void z_c2r_body(
     constexpr int M = N / 2, K = M + 1;
     using Z = zshape<M, EMAX, THREADS>;
     constexpr int E = Z::E, TPT = Z::TPT, RPB = Z::RPB;
-    constexpr int PS = first_radix_shift<E>::value, MP = padded_len<M, PS>::value;
+    constexpr int RM = radix_cap<T>();
+    constexpr int PS = first_radix_shift<E, RM>::value, MP = padded_len<M, PS>::value;
     __shared__ cx<T> lds[RPB * MP];
 
     const int rl = threadIdx.x / TPT;
@@ -250,7 +258,7 @@ __device__ __forceinline__ void z_c2r_body(
         a[m] = cx<T>{s.x - d.y, s.y + d.x};
     }
     __syncthreads();
-    fft_regs<T, M, E, +1>(a, t, tw, 2, xch_full<T, idx_rows<PS>>{lds, ix});
+    fft_regs<T, M, E, +1, RM>(a, t, tw, 2, xch_full<T, idx_rows<PS>>{lds, ix});
     if (!valid) return;
     cx<T>* dst = reinterpret_cast<cx<T>*>(out + row * map.rs);
 #pragma unroll
@@ -327,7 +335,8 @@ __global__ __launch_bounds__(TC * N / E) void k_strided(
     constexpr int TPT = N / E;
     constexpr bool SPLIT = XP == 2;
     static_assert(XP == 1 || XP == 2, "XP: whole values (1) or real/imaginary halves (2)");
-    constexpr int PS = first_radix_shift<E>::value;
+    constexpr int RM = radix_cap<T, MF>();
+    constexpr int PS = first_radix_shift<E, RM>::value;
     constexpr int NP = padded_len<N, PS>::value;
     __shared__ cx<T> lds[(NP * TC + XP - 1) / XP];
     using IX = idx_cols<TC, PS>;
@@ -376,10 +385,10 @@ __global__ __launch_bounds__(TC * N / E) void k_strided(
             }
         }
         if constexpr (SPLIT)
-            fft_regs<T, N, E, S>(a, t, tw, 1,
-                                 xch_split<T, IX>{reinterpret_cast<T*>(lds), IX{c}});
+            fft_regs<T, N, E, S, RM>(a, t, tw, 1,
+                                     xch_split<T, IX>{reinterpret_cast<T*>(lds), IX{c}});
         else
-            fft_regs<T, N, E, S>(a, t, tw, 1, xch_full<T, IX>{lds, IX{c}});
+            fft_regs<T, N, E, S, RM>(a, t, tw, 1, xch_full<T, IX>{lds, IX{c}});
     } else {
         // First radix-16 stage on the matrix cores.  The wave's 64 butterflies
         // (those of its own threads, j = t for thread (c, t)) go in two groups

@@ -89,7 +89,9 @@ struct zshape {
 // rows): FP64 R2C 8 elements per thread in 256-thread workgroups up to
 // N = 512, 16 per thread in 128-thread ones for N = 1024 and 2048 (7-8%
 // faster there), 32 per thread for N = 4096; FP64 C2R 16 per thread in
-// 64-thread workgroups; FP32 32 per thread in 64-thread ones.
+// 64-thread workgroups; FP32 32 per thread, in 256-thread workgroups for the
+// R2C from N = 1024 up (4-10% faster with the radix-32 stages) and 64-thread
+// ones otherwise.
 // Workgroups are dealt to XCDs in contiguous ranges by the C2R at every N
 // (3-5%) and by the R2C from N = 1024 up (2-3%).  The C2R also stores its
 // line-aligned
@@ -99,7 +101,8 @@ template <typename T, bool FWD, int N>
 struct zcfg {
     static constexpr bool F64 = sizeof(T) == 8;
     static constexpr int EMAX = F64 ? (FWD ? (N >= 4096 ? 32 : N >= 1024 ? 16 : 8) : 16) : 32;
-    static constexpr int THREADS = F64 && FWD ? (N >= 1024 ? 128 : 256) : 64;
+    static constexpr int THREADS =
+        F64 ? (FWD ? (N >= 1024 ? 128 : 256) : 64) : (FWD && N >= 1024 ? 256 : 64);
     static constexpr bool REMAP = !FWD || N >= 1024;
     static constexpr bool NTS = !FWD;
 };

@@ -351,8 +351,8 @@ def main():
     args = parse()
     if args.gpus != 1:
         print(f"bench.py measures one GPU's share of the transform; --gpus "
-              f"{args.gpus} is not supported (this build drives one GPU, and the "
-              f"multi-GPU exchange is not part of it).", file=sys.stderr)
+              f"{args.gpus} is not supported (the library drives one GPU; the "
+              f"exchange between GPUs belongs to the caller).", file=sys.stderr)
         sys.exit(2)
     if not torch.cuda.is_available():
         print("bench.py needs a GPU", file=sys.stderr)

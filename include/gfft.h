@@ -40,7 +40,7 @@ extern "C" {
 typedef enum {
     GFFT_OK = 0,
     GFFT_E_INVALID_ARG = -1, /* NULL pointer, bad sign, aliasing, bad enum  */
-    GFFT_E_UNSUPPORTED = -2, /* size/flag combination this build lacks      */
+    GFFT_E_UNSUPPORTED = -2, /* size/flag combination not supported         */
     GFFT_E_ALIGN = -3,       /* a data pointer is not 16-byte aligned       */
     GFFT_E_NOMEM = -4,       /* plan tables could not be allocated          */
     GFFT_E_HIP = -5,         /* a HIP runtime call or kernel launch failed  */

@@ -66,10 +66,18 @@ def test_pencil_pipeline_equals_full_transform(n, pr, pc):
     """Every x-pencil element equals F(x = r X + x_l, y = r' N/pr + g_l Y +
     y_l, kz = c w0 + kz_l) of the full-grid transform; p = pr pc exceeds N
     in the last cases."""
+    assert _pipeline_error(n, pr, pc) <= 1e-12
+
+
+def _pipeline_error(n, pr, pc):
+    """Largest deviation of the pencil pipeline from the full transform,
+    relative to max |F|; the expected index of each element is written out
+    here from the layout definitions, independently of the oracle's."""
     f = synth.uniform((n, n, n), 900 + n + pr + pc, torch.float64, "cpu").numpy()
     F = oracle.r2c3d(f)
     x, y, w0 = n // pr, n // pc, n // (2 * pc)
     xp, _ = _forward(f, n, pr, pc)
+    worst = 0.0
     for (rp, c), got in xp.items():
         k0, k1 = oracle.pencil_kz_range(n, pc, c)
         if pr <= pc:
@@ -83,7 +91,44 @@ def test_pencil_pipeline_equals_full_transform(n, pr, pc):
                                          np.arange(k1 - k0), indexing="ij")
             want = F[r_ * x + x_, rp * (n // pr) + y_, c * w0 + k_]
             assert got.shape == (pr, x, n // pr, k1 - k0)
-        assert np.max(np.abs(got - want)) <= 1e-12 * np.max(np.abs(F))
+        worst = max(worst, np.max(np.abs(got - want)) / np.max(np.abs(F)))
+    return worst
+
+
+def _mutants():
+    """Plausible mistakes in the pencil layouts, one per oracle function."""
+    orig = {k: getattr(oracle, k) for k in ("pencil_kz_range", "pencil_exchange1",
+                                             "pencil_exchange2", "pencil_send", "pencil_y_c2c")}
+
+    def nyquist_first(n, pc, c):
+        w0 = n // (2 * pc)
+        return c * w0 + (c > 0), (c + 1) * w0 + 1
+
+    def reversed_blocks(sends, x, y):
+        return orig["pencil_exchange1"](sends[::-1], x, y)
+
+    def shifted_peers(ypencils, pr):
+        out = orig["pencil_exchange2"](ypencils, pr)
+        return out[1:] + out[:1]
+
+    def transposed_chunks(rows, pc):
+        return orig["pencil_send"](np.ascontiguousarray(np.swapaxes(rows, -2, -3))
+                                   .reshape(rows.shape), pc)
+
+    def wrong_axis(ypencil, sign, method=None):
+        return oracle.c2c_axis(ypencil, -3, sign, method)
+
+    return {"pencil_kz_range": nyquist_first, "pencil_exchange1": reversed_blocks,
+            "pencil_exchange2": shifted_peers, "pencil_send": transposed_chunks,
+            "pencil_y_c2c": wrong_axis}
+
+
+@pytest.mark.parametrize("name", ["pencil_kz_range", "pencil_exchange1", "pencil_exchange2",
+                                  "pencil_send", "pencil_y_c2c"])
+def test_pencil_pins_catch_planted_mistakes(name, monkeypatch):
+    monkeypatch.setattr(oracle, name, _mutants()[name])
+    worst = max(_pipeline_error(16, pr, pc) for pr, pc in ((2, 4), (4, 2)))
+    assert worst > 1e-6, f"the pencil pins missed the planted mistake in {name}"
 
 
 @pytest.mark.parametrize("n,pr,pc", CASES[2:])

@@ -98,6 +98,31 @@ def test_c3_1024cubed_sampled_kz_planes_and_round_trip():
     _free()
 
 
+def test_c3_1024cubed_fp32_sampled_kz_planes():
+    """The FP32 bulk path at the benchmark size and launches: sampled kz
+    planes against the FP64 oracle on the same (exactly upcast) values, and
+    the round trip."""
+    n = 1024
+    p = Plan(n, torch.float32)
+    x = synth.uniform(p.real_shape, 3, torch.float32, "cuda")
+    F = p.r2c(x)
+    kz = [0, 3, 300, 512]
+    Fs = host(F[0, :, :, kz])
+    torch.cuda.synchronize()
+    f = x[0].cpu().numpy().astype(np.float64)
+    ref = oracle.r2c3d_kz_planes(f, kz)
+    del f
+    err = rel_l2(Fs, ref)
+    print(f"c3 FP32 1024^3 sampled kz planes {kz}: rel-L2 {err:.3e}")
+    assert err <= 5e-6
+    y = p.c2r(F, scale=1.0 / n ** 3)
+    rt = (torch.linalg.vector_norm(y - x) / torch.linalg.vector_norm(x)).item()
+    print(f"c3 FP32 round trip rel-L2 {rt:.3e}")
+    assert rt <= 5e-6
+    del F, x, y, p
+    _free()
+
+
 def test_c4_4096_slab_share_of_64_ranks():
     n, ranks = 4096, 64
     X = n // ranks

@@ -101,3 +101,33 @@ def test_fp64_central_differences_energy_and_poisson():
                 fd = (L(u + eps * d).item() - L(u - eps * d).item()) / (2 * eps)
                 an = torch.sum(u.grad * d).item()
                 assert abs(fd - an) <= 1e-8 * max(1.0, abs(an)), (L.__name__, fd, an)
+
+
+def test_adjoint_dot_products_at_1024():
+    """Both adjoints at the benchmark size (1024^3 FP64, the launches the
+    bench times), through the dot-product identities over all 2^30 points."""
+    import synth
+    n = 1024
+    p = Plan(n, torch.float64)
+    f = synth.uniform(p.real_shape, 31, torch.float64, "cuda")
+    G = torch.view_as_complex(synth.uniform(p.spectrum_shape + (2,), 32, torch.float64, "cuda"))
+    Ff = p.r2c(f)
+    lhs = sum(torch.sum(torch.real(torch.conj(Ff[0, s:s + 64]) * G[0, s:s + 64])).item()
+              for s in range(0, n, 64))
+    del Ff
+    At = p.r2c_adjoint(G.clone())
+    rhs = sum(torch.sum(f[0, s:s + 64] * At[0, s:s + 64]).item() for s in range(0, n, 64))
+    del At
+    print(f"R2C adjoint identity at 1024^3: {lhs:.12e} vs {rhs:.12e}")
+    assert abs(lhs - rhs) <= 1e-11 * abs(lhs)
+    h = f                                   # reuse: any real field
+    Cg = p.c2r(G.clone())
+    lhs = sum(torch.sum(Cg[0, s:s + 64] * h[0, s:s + 64]).item() for s in range(0, n, 64))
+    del Cg
+    Bt = p.c2r_adjoint(h)
+    rhs = sum(torch.sum(torch.real(torch.conj(G[0, s:s + 64]) * Bt[0, s:s + 64])).item()
+              for s in range(0, n, 64))
+    print(f"C2R adjoint identity at 1024^3: {lhs:.12e} vs {rhs:.12e}")
+    assert abs(lhs - rhs) <= 1e-11 * abs(lhs)
+    del Bt, G, f, p
+    torch.cuda.empty_cache()

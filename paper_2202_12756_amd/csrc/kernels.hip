@@ -316,8 +316,12 @@ struct sshape {
     static constexpr bool WIDE = AX == 0 || N >= 2048;
     static constexpr int E = MFMA ? 16 : N >= 512 ? 32 : 16;
     static constexpr int TPT = N / E;
-    static constexpr int MAXT = F64 ? (WIDE ? 512 : 256) : (N >= 2048 || MFMA ? 1024 : 512);
-    static constexpr int LDS = (F64 ? WIDE : N >= 2048) ? 131072 : 65536;
+    // FP32 y lines of N = 2048: two 8-column tiles per CU (9% faster than
+    // one 16-column tile)
+    static constexpr bool Y2048 = !F64 && !MFMA && AX == 0 && N == 2048;
+    static constexpr bool BIG32 = N >= 2048 && !Y2048;
+    static constexpr int MAXT = F64 ? (WIDE ? 512 : 256) : (BIG32 || MFMA ? 1024 : 512);
+    static constexpr int LDS = (F64 ? WIDE : BIG32) ? 131072 : 65536;
     static constexpr int TC_T = MAXT / TPT;
     static constexpr int CAP = (256 / TPT) > 16 ? (256 / TPT) : 16;
     static constexpr int FULL = LDS / (N * int(sizeof(cx<T>)));

@@ -209,3 +209,28 @@ def test_pencil_4096_share_sampled(col):
         assert rel_l2(xp[0, :, gl, :, yl, kl].reshape(-1).cpu().numpy(), ref) <= 1e-13
     del xp, x0
     torch.cuda.empty_cache()
+
+
+@pytest.mark.parametrize("grid", [(2, 4), (8, 2)])
+def test_pencil_batched_y_and_x_passes(grid):
+    """batch = 3 grids back to back through the y and x passes (and the
+    second-exchange pack for pr > pc), each grid against the oracle."""
+    n, (pr, pc) = 32, grid
+    for dtype in (torch.float64, torch.float32):
+        p = PencilPlan(n, dtype, (pr, pc), pc - 1, batch=3)
+        yp, ypref = cplx_input(p.ypencil_shape, 1500 + pr, dtype)
+        p.y_c2c(yp, +1)
+        xp, xpref = cplx_input(p.xpencil_shape, 1510 + pr, dtype)
+        p.x_c2c(xp, -1)
+        torch.cuda.synchronize()
+        for b in range(3):
+            assert rel_l2(host(yp)[b], oracle.pencil_y_c2c(ypref[b], +1)) <= TOL[dtype]
+            if p.h > 1:
+                want = oracle.x_c2c(xpref[b].reshape(n, n // pr, -1), -1).reshape(xpref[b].shape)
+            else:
+                want = oracle.pencil_x_c2c(xpref[b], -1)
+            assert rel_l2(host(xp)[b], want) <= TOL[dtype]
+        if p.h > 1:
+            send = p.pack2(yp)
+            torch.cuda.synchronize()
+            assert np.array_equal(host(send), oracle.pencil_pack2(host(yp), p.h))

@@ -148,3 +148,45 @@ def test_product_path_has_no_cpu_fallback():
             assert "import oracle" not in src and "from oracle" not in src, fn
             assert "torch.fft" not in src, fn
             assert "numpy.fft" not in src and "np.fft" not in src, fn
+
+
+C_CLIENT = r"""
+#include <stdio.h>
+#include <string.h>
+#include "gfft.h"
+int main(void) {
+    gfft_plan *p = 0;
+    /* host-side validation runs before any device query */
+    if (gfft_plan_create(&p, 48, GFFT_F64, 48, 1, 0) != GFFT_E_UNSUPPORTED) return 1;
+    if (gfft_pencil_plan_create(&p, 64, GFFT_F32, 2, 64, 0, 1, 0) != GFFT_E_UNSUPPORTED) return 2;
+    if (p != 0) return 3;
+    if (gfft_plan_destroy(0) != GFFT_OK) return 4;
+    if (strcmp(gfft_status_string(GFFT_E_ALIGN), "data pointer not 16-byte aligned") != 0) return 5;
+    if (gfft_version() < 100) return 6;
+    gfft_status st = gfft_plan_create(&p, 64, GFFT_F64, 64, 1, 0);
+    printf("%d\n", (int)st);
+    if (st == GFFT_OK) gfft_plan_destroy(p);
+    return 0;
+}
+"""
+
+
+def test_header_is_c_and_the_library_links_from_c(tmp_path):
+    """include/gfft.h compiles as C99, and a C program linked against
+    libgfft.so gets the host-side checks and status strings."""
+    import shutil
+    import subprocess
+    gcc = shutil.which("gcc")
+    if gcc is None:
+        pytest.skip("gcc not available")
+    lib = _lib.load()._name
+    src = tmp_path / "client.c"
+    src.write_text(C_CLIENT)
+    exe = tmp_path / "client"
+    subprocess.run([gcc, "-std=c99", "-Wall", "-Wextra", "-Werror", "-I", os.path.join(ROOT, "include"),
+                    str(src), lib, f"-Wl,-rpath,{os.path.dirname(lib)}", "-o", str(exe)],
+                   check=True)
+    r = subprocess.run([str(exe)], capture_output=True, text=True, timeout=60)
+    assert r.returncode == 0, (r.returncode, r.stderr)
+    st = int(r.stdout.strip())
+    assert st in (_lib.GFFT_OK, _lib.GFFT_E_NO_DEVICE)

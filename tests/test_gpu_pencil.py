@@ -234,3 +234,16 @@ def test_pencil_batched_y_and_x_passes(grid):
             send = p.pack2(yp)
             torch.cuda.synchronize()
             assert np.array_equal(host(send), oracle.pencil_pack2(host(yp), p.h))
+
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32], ids=["f64", "f32"])
+def test_pencil_x_pass_streaming_kernel(dtype):
+    """N = 512: the pencil x-pencil's strides are whole 128-byte lines, so
+    the x pass takes its non-temporal kernel; checked against the oracle."""
+    n, pr, pc = 512, 2, 4
+    p = PencilPlan(n, dtype, (pr, pc), pc - 1)
+    assert (p.y * p.w * (16 if dtype == torch.float64 else 8)) % 128 == 0
+    xp, xpref = cplx_input(p.xpencil_shape, 1600, dtype)
+    p.x_c2c(xp, +1)
+    torch.cuda.synchronize()
+    assert rel_l2(host(xp)[0], oracle.pencil_x_c2c(xpref[0], +1)) <= TOL[dtype]

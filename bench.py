@@ -44,7 +44,7 @@ def parse():
 
 
 TRAFFIC_FILE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "profiles",
-                            "c3_1024_f64_pmc_traffic.md")
+                            "full_1024_f64_pmc_traffic.md")
 
 
 def kernel_source_hash() -> str:

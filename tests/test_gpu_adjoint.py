@@ -71,7 +71,7 @@ def test_autograd_energy_loss_gradient():
 
 
 def test_fp64_central_differences_energy_and_poisson():
-    """Both c5 losses through the FP64 autograd path: central differences
+    """Both spectral losses (energy and Poisson) through the FP64 autograd path: central differences
     (eps = 1e-3, exact for a quadratic loss up to rounding) along seeded
     uniform directions agree with the hand-written adjoint to 1e-8."""
     import synth

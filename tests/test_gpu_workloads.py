@@ -1,13 +1,13 @@
 """GPU parity at the benchmark workloads' own shapes.
 
-c1  64^3 FP64 uniform: every bin against both oracle methods.
-c2  512^3 Kolmogorov-spectrum field, FP64 and FP32: every bin.
-c3  1024^3 FP64 uniform (the benchmark workload, same launches): whole
-    kz-planes sampled from the oracle, plus the round trip.
-c4  rank 0's slab of a 4096^3 grid over 64 ranks: sampled planes of the
-    local 2D R2C in send order, the send blocks against the standalone pack
-    bit for bit, and sampled columns of the x pass on a received pencil.
-c5  8 x 256^3 FP32 fields: spectral-energy and Poisson losses through the
+64^3 FP64 uniform: every bin against both oracle methods.
+512^3 Kolmogorov-spectrum field, FP64 and FP32: every bin.
+1024^3 uniform (the benchmark workload, same launches), FP64 and FP32:
+    whole kz-planes sampled from the oracle, plus the round trip.
+Rank 0's slab of a 4096^3 grid over 64 ranks: sampled planes of the local
+    2D R2C in send order, the send blocks against the standalone pack bit
+    for bit, and sampled columns of the x pass on a received pencil.
+8 x 256^3 FP32 fields: spectral-energy and Poisson losses through the
     autograd wrappers against the FP64 oracle gradients and finite
     differences.
 """
@@ -30,7 +30,7 @@ def _free():
     torch.cuda.empty_cache()
 
 
-def test_c1_64cubed_fp64_both_oracle_methods():
+def test_64cubed_fp64_both_oracle_methods():
     n = 64
     p = Plan(n, torch.float64)
     x = synth.uniform(p.real_shape, 1, torch.float64)
@@ -53,7 +53,7 @@ def kolmogorov_512():
 
 
 @pytest.mark.parametrize("dtype", [torch.float64, torch.float32], ids=["f64", "f32"])
-def test_c2_512cubed_kolmogorov(kolmogorov_512, dtype):
+def test_512cubed_kolmogorov(kolmogorov_512, dtype):
     n = 512
     f = kolmogorov_512
     xin = torch.from_numpy(f).to(dtype)          # FP32: RNE of the FP64 field
@@ -64,19 +64,19 @@ def test_c2_512cubed_kolmogorov(kolmogorov_512, dtype):
     Fh = host(F)[0]
     ref = oracle.r2c3d(fin)
     err = rel_l2(Fh, ref)
-    print(f"c2 512^3 {dtype}: forward rel-L2 vs FP64 oracle {err:.3e}")
+    print(f"512^3 {dtype}: forward rel-L2 vs FP64 oracle {err:.3e}")
     assert err <= TOL[dtype]
     del Fh, ref
     back = p.c2r(F, scale=1.0 / n ** 3)
     torch.cuda.synchronize()
     rt = rel_l2(host(back)[0], fin)
-    print(f"c2 512^3 {dtype}: round trip rel-L2 {rt:.3e}")
+    print(f"512^3 {dtype}: round trip rel-L2 {rt:.3e}")
     assert rt <= TOL[dtype]
     del F, back, p
     _free()
 
 
-def test_c3_1024cubed_sampled_kz_planes_and_round_trip():
+def test_1024cubed_sampled_kz_planes_and_round_trip():
     n = 1024
     p = Plan(n, torch.float64)
     x = synth.uniform(p.real_shape, 3, torch.float64, "cuda")
@@ -88,17 +88,17 @@ def test_c3_1024cubed_sampled_kz_planes_and_round_trip():
     ref = oracle.r2c3d_kz_planes(f, kz)
     del f
     err = rel_l2(Fs, ref)
-    print(f"c3 1024^3 sampled kz planes {kz}: rel-L2 {err:.3e}")
+    print(f"1024^3 sampled kz planes {kz}: rel-L2 {err:.3e}")
     assert err <= 1e-13
     y = p.c2r(F, scale=1.0 / n ** 3)
     rt = (torch.linalg.vector_norm(y - x) / torch.linalg.vector_norm(x)).item()
-    print(f"c3 round trip rel-L2 {rt:.3e}")
+    print(f"1024^3 round trip rel-L2 {rt:.3e}")
     assert rt <= 1e-13
     del F, x, y, p
     _free()
 
 
-def test_c3_1024cubed_fp32_sampled_kz_planes():
+def test_1024cubed_fp32_sampled_kz_planes():
     """The FP32 bulk path at the benchmark size and launches: sampled kz
     planes against the FP64 oracle on the same (exactly upcast) values, and
     the round trip."""
@@ -113,17 +113,17 @@ def test_c3_1024cubed_fp32_sampled_kz_planes():
     ref = oracle.r2c3d_kz_planes(f, kz)
     del f
     err = rel_l2(Fs, ref)
-    print(f"c3 FP32 1024^3 sampled kz planes {kz}: rel-L2 {err:.3e}")
+    print(f"1024^3 FP32 sampled kz planes {kz}: rel-L2 {err:.3e}")
     assert err <= 5e-6
     y = p.c2r(F, scale=1.0 / n ** 3)
     rt = (torch.linalg.vector_norm(y - x) / torch.linalg.vector_norm(x)).item()
-    print(f"c3 FP32 round trip rel-L2 {rt:.3e}")
+    print(f"1024^3 FP32 round trip rel-L2 {rt:.3e}")
     assert rt <= 5e-6
     del F, x, y, p
     _free()
 
 
-def test_c4_4096_slab_share_of_64_ranks():
+def test_4096_slab_share_of_64_ranks():
     n, ranks = 4096, 64
     X = n // ranks
     k = n // 2 + 1
@@ -139,7 +139,7 @@ def test_c4_4096_slab_share_of_64_ranks():
                     for pl in planes])
     ref = oracle.r2c2d_planes(src)
     err = rel_l2(got, ref)
-    print(f"c4 2D R2C on planes {planes}: rel-L2 {err:.3e}")
+    print(f"4096^3/64 2D R2C on planes {planes}: rel-L2 {err:.3e}")
     assert err <= 1e-13
     del got, ref, src
     # the fused send order is exactly the standalone pack of the natural result
@@ -163,14 +163,14 @@ def test_c4_4096_slab_share_of_64_ranks():
     after = host(pen.reshape(n, X * k)[:, cols.cuda()])
     ref = oracle.c2c_axis(before, 0, -1)
     err = rel_l2(after, ref)
-    print(f"c4 x pass on 512 sampled columns: rel-L2 {err:.3e}")
+    print(f"4096^3/64 x pass on 512 sampled columns: rel-L2 {err:.3e}")
     assert err <= 1e-13
     del pen, pen_plan
     _free()
 
 
 @pytest.fixture(scope="module")
-def c5_fields():
+def fields_8x256():
     n, b = 256, 8
     fs = []
     for i in range(b):
@@ -184,18 +184,18 @@ def _energy_loss_gpu(u, plan, wk2):
     return torch.sum(wk2 * (F.real.double() ** 2 + F.imag.double() ** 2))
 
 
-def test_c5_energy_loss_gradient_fp32(c5_fields):
+def test_8x256_energy_loss_gradient_fp32(fields_8x256):
     n, b = 256, 8
     plan = Plan(n, torch.float32, batch=b)
     wk2 = torch.from_numpy(oracle.half_weights(n) * oracle.k_squared(n)).cuda()
-    u = torch.from_numpy(c5_fields).cuda().reshape(plan.real_shape).requires_grad_(True)
+    u = torch.from_numpy(fields_8x256).cuda().reshape(plan.real_shape).requires_grad_(True)
     L = _energy_loss_gpu(u, plan, wk2)
     L.backward()
     g = host(u.grad)
     # FP64 oracle gradient per field, from the same (FP32) input values
-    errs = [rel_l2(g[i], oracle.energy_loss_grad(c5_fields[i].astype(np.float64)))
+    errs = [rel_l2(g[i], oracle.energy_loss_grad(fields_8x256[i].astype(np.float64)))
             for i in range(b)]
-    print(f"c5 energy-loss gradient rel-L2 per field: max {max(errs):.3e}")
+    print(f"8x256^3 energy-loss gradient rel-L2 per field: max {max(errs):.3e}")
     assert max(errs) <= TOL[torch.float32]
     # central finite differences (eps = 1e-3) along seeded directions from the
     # same spectral class as the fields: white-noise directions are nearly
@@ -217,7 +217,7 @@ def test_c5_energy_loss_gradient_fp32(c5_fields):
     _free()
 
 
-def test_c5_poisson_loss_gradient_fp32(c5_fields):
+def test_8x256_poisson_loss_gradient_fp32(fields_8x256):
     n, b = 256, 8
     plan = Plan(n, torch.float32, batch=b)
     k2 = oracle.k_squared(n)
@@ -237,7 +237,7 @@ def test_c5_poisson_loss_gradient_fp32(c5_fields):
         fi = srcs[i].astype(np.float64)
         errs_u.append(rel_l2(uh[i], oracle.poisson(fi)))
         errs_g.append(rel_l2(g[i], oracle.poisson_loss_grad(fi)))
-    print(f"c5 Poisson: solution rel-L2 max {max(errs_u):.3e}, gradient max {max(errs_g):.3e}")
+    print(f"8x256^3 Poisson: solution rel-L2 max {max(errs_u):.3e}, gradient max {max(errs_g):.3e}")
     assert max(errs_u) <= TOL[torch.float32]
     assert max(errs_g) <= TOL[torch.float32]
     del f, u, plan

@@ -40,6 +40,9 @@ def parse():
                     help="x-planes (and pencil columns) in the oracle sample")
     ap.add_argument("--traffic", default=None,
                     help="PMC traffic summary (default: the committed 1024^3 FP64 one)")
+    ap.add_argument("--only", choices=sorted(ONLY), default=None,
+                    help="time one other workload group alone and print its JSON "
+                         "(for profiling it); no 1024^3 line")
     return ap.parse_args()
 
 
@@ -219,6 +222,7 @@ def variants(n: int, steps: int, x64: torch.Tensor, dev) -> dict:
                                                           / 1e9 / PEAK_HBM_GBS, 4)}
     del G, h, p64
     torch.cuda.empty_cache()
+    out.update(slab_share_4096(steps, dev))
     out.update(pencil_variants(steps, dev))
     out.update(graph_variants(steps, dev))
     out.update(full_grid_2048(steps, dev))
@@ -304,6 +308,41 @@ def graph_variants(steps: int, dev) -> dict:
     return out
 
 
+def slab_share_4096(steps: int, dev) -> dict:
+    """Rank 0's slab share of a 4096^3 FP64 grid over 64 ranks: the local
+    2D R2C of the 64 x 4096 x 4096 real slab with the z pass storing the 64
+    all-to-all send blocks of 64 x 64 x 2049 (pack fused), the y pass on the
+    send blocks, and the x pass on a synthetic received pencil [4096][64][2049]
+    (the exchange is the caller's).  Bytes per pass: z reads the slab and
+    writes the send buffer, y and x read and write their array in place."""
+    import synth
+    from paper_2202_12756_amd import Plan
+
+    n, ranks = 4096, 64
+    X = n // ranks
+    p = Plan(n, torch.float64, slab_x=X, fuse_pack=True, device=dev)
+    xr = synth.uniform(p.real_shape, 4, torch.float64, dev)
+    send = p.empty_spectrum()
+    pen = torch.view_as_complex(synth.uniform(p.pencil_shape + (2,), 40, torch.float64, dev))
+    ms = {"z_r2c_send": time_pairs(lambda: p.z_r2c(xr, send), steps, 2),
+          "y_fwd": time_pairs(lambda: p.y_c2c(send, -1), steps, 2),
+          "x_fwd": time_pairs(lambda: p.x_c2c(pen, -1), steps, 2)}
+    bts = {"z_r2c_send": xr.numel() * 8 + send.numel() * 16,
+           "y_fwd": 2 * send.numel() * 16, "x_fwd": 2 * pen.numel() * 16}
+    chain = time_pairs(lambda: (p.r2c(xr, send), p.x_c2c(pen, -1)), steps, 2)
+    out = {"slab_4096_p64_f64": {
+        "real_slab": f"{X}x{n}x{n}", "send_blocks": f"{ranks}x{X}x{X}x{n // 2 + 1}",
+        "pass_ms": {k: round(v, 4) for k, v in ms.items()},
+        "pass_GBps": {k: round(bts[k] / (ms[k] * 1e-3) / 1e9, 1) for k in ms},
+        "chain_ms": round(chain, 4),
+        "chain_hbm_roofline_frac": round(sum(bts.values()) / (chain * 1e-3) / 1e9
+                                         / PEAK_HBM_GBS, 4),
+    }}
+    del p, xr, send, pen
+    torch.cuda.empty_cache()
+    return out
+
+
 def pencil_variants(steps: int, dev) -> dict:
     """One rank's local forward chain of a pencil-decomposed 4096^3 FP64 grid
     (z R2C into the first-exchange order, y pass on the received y-pencil,
@@ -347,6 +386,11 @@ def pencil_variants(steps: int, dev) -> dict:
     return out
 
 
+# workload groups that --only runs by themselves
+ONLY = {"slab_4096": slab_share_4096, "pencil_4096": pencil_variants,
+        "full_2048": full_grid_2048, "graphs": graph_variants}
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -367,6 +411,10 @@ def main():
     k = n // 2 + 1
     dev = torch.device("cuda", 0)
     torch.cuda.set_device(dev)
+    if args.only:
+        print(json.dumps({"only": args.only, "steps": args.steps,
+                          "variants": ONLY[args.only](args.steps, dev)}), flush=True)
+        return
     plan = Plan(n, dtype, device=dev)
     x = synth.uniform(plan.real_shape, args.seed, dtype, dev)
     F = plan.empty_spectrum()

@@ -1,6 +1,6 @@
 """bench.py host logic without a GPU: refusal of several GPUs, the FLOP
-convention, and the recorded-traffic lookup (valid only for the kernel
-sources it was measured on)."""
+convention, the recorded-traffic lookup (valid only for the kernel
+sources it was measured on) and the workload groups of --only."""
 import os
 import subprocess
 import sys
@@ -32,3 +32,12 @@ def test_recorded_traffic_requires_matching_sources(tmp_path):
                                   "kernel_source_sha256_16: 0000000000000000"))
     assert bench.recorded_traffic(str(stale), "x_fwd") is None
     assert bench.recorded_traffic(str(tmp_path / "missing.md"), "x_fwd") is None
+
+
+def test_only_groups():
+    # every group --only offers is one of the variant functions of the full run
+    assert set(bench.ONLY) == {"slab_4096", "pencil_4096", "full_2048", "graphs"}
+    assert all(callable(f) for f in bench.ONLY.values())
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--only", "nope"],
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode == 2 and "invalid choice" in r.stderr

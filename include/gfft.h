@@ -128,8 +128,9 @@ typedef struct {
  *            GFFT_MFMA_BF16X3 (or 0).
  * On success *out receives the plan.  The plan owns small device tables
  * (FP64-derived twiddle factors rounded once to the working precision) on
- * the device that is current at creation; exec calls must run with that
- * device current.
+ * the device that is current at creation; exec, pack and pass calls must run
+ * with that device current (and on a stream of it), and return
+ * GFFT_E_INVALID_ARG, before any launch, when another device is current.
  */
 gfft_status gfft_plan_create(gfft_plan **out, int64_t n, gfft_dtype dtype,
                              int64_t slab_x, int64_t batch, uint32_t flags);

@@ -187,6 +187,15 @@ gfft::line_map xmap(const gfft_plan* p) {
 
 gfft_status hip_status(hipError_t e) { return e == hipSuccess ? GFFT_OK : GFFT_E_HIP; }
 
+// The plan's tables live on the device that was current at creation, and
+// its kernels must run there: exec calls refuse any other current device
+// (checked last, after the arguments).
+gfft_status check_device(const gfft_plan* p) {
+    int d = -1;
+    if (hipGetDevice(&d) != hipSuccess) return GFFT_E_HIP;
+    return d == p->device ? GFFT_OK : GFFT_E_INVALID_ARG;
+}
+
 hipStream_t as_stream(void* s) { return static_cast<hipStream_t>(s); }
 
 bool f64(const gfft_plan* p) { return p->dtype == GFFT_F64; }
@@ -246,6 +255,7 @@ gfft_status forward(const gfft_plan* p, const void* in, void* out, double scale,
     if (st != GFFT_OK) return st;
     if (p->pencil) return GFFT_E_UNSUPPORTED;
     if (!std::isfinite(scale)) return GFFT_E_INVALID_ARG;
+    if ((st = check_device(p)) != GFFT_OK) return st;
     hipStream_t s = as_stream(stream);
     if ((st = run_z_r2c(p, in, out, scale, weighted, s)) != GFFT_OK) return st;
     if ((st = run_y(p, out, -1, s)) != GFFT_OK) return st;
@@ -259,6 +269,7 @@ gfft_status inverse(const gfft_plan* p, void* in, void* out, double scale, bool 
     if (st != GFFT_OK) return st;
     if (p->pencil) return GFFT_E_UNSUPPORTED;
     if (!std::isfinite(scale)) return GFFT_E_INVALID_ARG;
+    if ((st = check_device(p)) != GFFT_OK) return st;
     hipStream_t s = as_stream(stream);
     if (p->p == 1 && (st = run_x(p, in, +1, s)) != GFFT_OK) return st;
     if ((st = run_y(p, in, +1, s)) != GFFT_OK) return st;
@@ -275,6 +286,7 @@ gfft_status pencil_pack(const gfft_plan* p, const void* src, void* dst, bool to_
     if (st != GFFT_OK || (st = check_ptr(dst)) != GFFT_OK) return st;
     const int64_t bytes = p->batch * p->pc * p->x * p->y * p->w * 2 * elt(p);
     if (overlap(src, bytes, dst, bytes)) return GFFT_E_INVALID_ARG;
+    if ((st = check_device(p)) != GFFT_OK) return st;
     return hip_status(gfft::launch_pack(f64(p), src, dst, p->batch * p->pc * p->h * p->x,
                                         p->lg_x, p->lg_h, p->y, p->y / p->h, p->w, to_send,
                                         as_stream(stream)));
@@ -522,6 +534,7 @@ gfft_status gfft_pack_slab_for_alltoall(const gfft_plan* p, const void* src, voi
     gfft_status st = check_ptr(src);
     if (st != GFFT_OK || (st = check_ptr(dst)) != GFFT_OK) return st;
     if (overlap(src, cplx_bytes(p), dst, cplx_bytes(p))) return GFFT_E_INVALID_ARG;
+    if ((st = check_device(p)) != GFFT_OK) return st;
     if (paper(p))
         return hip_status(gfft::launch_pack_rows(f64(p), src, dst, p->batch * p->x * p->n, p->k,
                                                  packmap(p), true, as_stream(stream)));
@@ -536,6 +549,7 @@ gfft_status gfft_unpack_slab_from_alltoall(const gfft_plan* p, const void* src, 
     gfft_status st = check_ptr(src);
     if (st != GFFT_OK || (st = check_ptr(dst)) != GFFT_OK) return st;
     if (overlap(src, cplx_bytes(p), dst, cplx_bytes(p))) return GFFT_E_INVALID_ARG;
+    if ((st = check_device(p)) != GFFT_OK) return st;
     if (paper(p))
         return hip_status(gfft::launch_pack_rows(f64(p), src, dst, p->batch * p->x * p->n, p->k,
                                                  packmap(p), false, as_stream(stream)));
@@ -547,7 +561,7 @@ gfft_status gfft_exec_x_c2c(const gfft_plan* p, void* pencil, int sign, void* st
     if (!p) return GFFT_E_INVALID_ARG;
     if (sign != -1 && sign != 1) return GFFT_E_INVALID_ARG;
     gfft_status st = check_ptr(pencil);
-    if (st != GFFT_OK) return st;
+    if (st != GFFT_OK || (st = check_device(p)) != GFFT_OK) return st;
     return run_x(p, pencil, sign, as_stream(stream));
 }
 
@@ -556,6 +570,7 @@ gfft_status gfft_exec_z_r2c(const gfft_plan* p, const void* in, void* out, doubl
     gfft_status st = check_r2c_args(p, in, out);
     if (st != GFFT_OK) return st;
     if (!std::isfinite(scale)) return GFFT_E_INVALID_ARG;
+    if ((st = check_device(p)) != GFFT_OK) return st;
     return run_z_r2c(p, in, out, scale, weighted != 0, as_stream(stream));
 }
 
@@ -563,7 +578,7 @@ gfft_status gfft_exec_y_c2c(const gfft_plan* p, void* data, int sign, void* stre
     if (!p) return GFFT_E_INVALID_ARG;
     if (sign != -1 && sign != 1) return GFFT_E_INVALID_ARG;
     gfft_status st = check_ptr(data);
-    if (st != GFFT_OK) return st;
+    if (st != GFFT_OK || (st = check_device(p)) != GFFT_OK) return st;
     return run_y(p, data, sign, as_stream(stream));
 }
 
@@ -572,6 +587,7 @@ gfft_status gfft_exec_z_c2r(const gfft_plan* p, const void* in, void* out, doubl
     gfft_status st = check_r2c_args(p, out, in);
     if (st != GFFT_OK) return st;
     if (!std::isfinite(scale)) return GFFT_E_INVALID_ARG;
+    if ((st = check_device(p)) != GFFT_OK) return st;
     return run_z_c2r(p, in, out, scale, weighted != 0, as_stream(stream));
 }
 

@@ -18,7 +18,23 @@ def _stream(device) -> int:
     return torch.cuda.current_stream(device).cuda_stream
 
 
-class Plan:
+def _resolve(device) -> torch.device:
+    """The plan's device with its index fixed (the current one if none is given)."""
+    dev = torch.device(device if device is not None else "cuda")
+    if dev.index is None:
+        dev = torch.device("cuda", torch.cuda.current_device())
+    return dev
+
+
+class _Exec:
+    def _exec(self, fn, *args):
+        """Call a library entry point with the plan's device current, on that
+        device's current torch stream (the library refuses any other device)."""
+        with torch.cuda.device(self.device):
+            _lib.check(fn(self._h, *args, _stream(self.device)), fn.__name__)
+
+
+class Plan(_Exec):
     """One GPU's share of an N^3 real FFT (full grid when slab_x == n).
 
     Layouts (C order, z fastest): real [batch, X, N, N]; half spectrum
@@ -46,7 +62,7 @@ class Plan:
         self.slab_x = int(slab_x if slab_x is not None else n)
         self.batch = int(batch)
         self.fuse_pack = bool(fuse_pack)
-        self.device = torch.device(device if device is not None else "cuda")
+        self.device = _resolve(device)
         self.mfma_terms = int(mfma_terms)
         self.inplace = bool(inplace)
         self.paper_order = bool(paper_order)
@@ -102,9 +118,7 @@ class Plan:
             raise TypeError(f"{what} must be a torch.Tensor")
         if t.dtype != dtype:
             raise TypeError(f"{what} must have dtype {dtype}, got {t.dtype}")
-        if t.device != self.device and not (
-                t.device.type == "cuda" and self.device.index is None
-                and t.device.index == torch.cuda.current_device()):
+        if t.device != self.device:
             raise ValueError(f"{what} must live on {self.device}")
         if not t.is_contiguous():
             raise ValueError(f"{what} must be contiguous")
@@ -134,8 +148,7 @@ class Plan:
         out = self.empty_spectrum() if out is None else out
         a = self._check(x, self.dtype, self._nreal(), "input")
         b = self._check(out, self.cdtype, self._ncplx(), "output")
-        _lib.check(_lib.gfft_exec_r2c(self._h, a, b, _stream(self.device)),
-                   "gfft_exec_r2c")
+        self._exec(_lib.gfft_exec_r2c, a, b)
         return out
 
     def c2r(self, g: torch.Tensor, out: torch.Tensor | None = None,
@@ -144,8 +157,7 @@ class Plan:
         out = self.empty_real() if out is None else out
         a = self._check(g, self.cdtype, self._ncplx(), "input")
         b = self._check(out, self.dtype, self._nreal(), "output")
-        _lib.check(_lib.gfft_exec_c2r(self._h, a, b, float(scale),
-                                      _stream(self.device)), "gfft_exec_c2r")
+        self._exec(_lib.gfft_exec_c2r, a, b, float(scale))
         return out
 
     def r2c_adjoint(self, g: torch.Tensor, out=None, scale: float = 1.0):
@@ -153,9 +165,7 @@ class Plan:
         out = self.empty_real() if out is None else out
         a = self._check(g, self.cdtype, self._ncplx(), "input")
         b = self._check(out, self.dtype, self._nreal(), "output")
-        _lib.check(_lib.gfft_exec_r2c_adjoint(self._h, a, b, float(scale),
-                                              _stream(self.device)),
-                   "gfft_exec_r2c_adjoint")
+        self._exec(_lib.gfft_exec_r2c_adjoint, a, b, float(scale))
         return out
 
     def c2r_adjoint(self, h: torch.Tensor, out=None, scale: float = 1.0):
@@ -163,9 +173,7 @@ class Plan:
         out = self.empty_spectrum() if out is None else out
         a = self._check(h, self.dtype, self._nreal(), "input")
         b = self._check(out, self.cdtype, self._ncplx(), "output")
-        _lib.check(_lib.gfft_exec_c2r_adjoint(self._h, a, b, float(scale),
-                                              _stream(self.device)),
-                   "gfft_exec_c2r_adjoint")
+        self._exec(_lib.gfft_exec_c2r_adjoint, a, b, float(scale))
         return out
 
     def pack(self, slab: torch.Tensor, out: torch.Tensor | None = None):
@@ -173,9 +181,7 @@ class Plan:
                            device=self.device) if out is None else out)
         a = self._check(slab, self.cdtype, self._ncplx(), "slab")
         b = self._check(out, self.cdtype, self._ncplx(), "send")
-        _lib.check(_lib.gfft_pack_slab_for_alltoall(self._h, a, b,
-                                                    _stream(self.device)),
-                   "gfft_pack_slab_for_alltoall")
+        self._exec(_lib.gfft_pack_slab_for_alltoall, a, b)
         return out
 
     def unpack(self, recv: torch.Tensor, out: torch.Tensor | None = None):
@@ -184,15 +190,12 @@ class Plan:
                if out is None else out)
         a = self._check(recv, self.cdtype, self._ncplx(), "recv")
         b = self._check(out, self.cdtype, self._ncplx(), "slab")
-        _lib.check(_lib.gfft_unpack_slab_from_alltoall(self._h, a, b,
-                                                       _stream(self.device)),
-                   "gfft_unpack_slab_from_alltoall")
+        self._exec(_lib.gfft_unpack_slab_from_alltoall, a, b)
         return out
 
     def x_c2c(self, pencil: torch.Tensor, sign: int):
         a = self._check(pencil, self.cdtype, self._npencil(), "pencil")
-        _lib.check(_lib.gfft_exec_x_c2c(self._h, a, int(sign),
-                                        _stream(self.device)), "gfft_exec_x_c2c")
+        self._exec(_lib.gfft_exec_x_c2c, a, int(sign))
         return pencil
 
     # ------------------------------------------------------------ in place
@@ -214,26 +217,23 @@ class Plan:
     def r2c_(self, buf: torch.Tensor):
         """In-place forward transform of the padded field in ``buf``."""
         a = self._inplace_ptr(buf)
-        _lib.check(_lib.gfft_exec_r2c(self._h, a, a, _stream(self.device)), "gfft_exec_r2c")
+        self._exec(_lib.gfft_exec_r2c, a, a)
         return buf
 
     def c2r_(self, buf: torch.Tensor, scale: float = 1.0):
         """In-place inverse; returns the real view of ``buf``."""
         a = self._inplace_ptr(buf)
-        _lib.check(_lib.gfft_exec_c2r(self._h, a, a, float(scale), _stream(self.device)),
-                   "gfft_exec_c2r")
+        self._exec(_lib.gfft_exec_c2r, a, a, float(scale))
         return self.real_view(buf)
 
     def r2c_adjoint_(self, buf: torch.Tensor, scale: float = 1.0):
         a = self._inplace_ptr(buf)
-        _lib.check(_lib.gfft_exec_r2c_adjoint(self._h, a, a, float(scale),
-                                              _stream(self.device)), "gfft_exec_r2c_adjoint")
+        self._exec(_lib.gfft_exec_r2c_adjoint, a, a, float(scale))
         return self.real_view(buf)
 
     def c2r_adjoint_(self, buf: torch.Tensor, scale: float = 1.0):
         a = self._inplace_ptr(buf)
-        _lib.check(_lib.gfft_exec_c2r_adjoint(self._h, a, a, float(scale),
-                                              _stream(self.device)), "gfft_exec_c2r_adjoint")
+        self._exec(_lib.gfft_exec_c2r_adjoint, a, a, float(scale))
         return buf
 
     # ------------------------------------------------------------ passes
@@ -241,24 +241,19 @@ class Plan:
         out = self.empty_spectrum() if out is None else out
         a = self._check(x, self.dtype, self._nreal(), "input")
         b = self._check(out, self.cdtype, self._ncplx(), "output")
-        _lib.check(_lib.gfft_exec_z_r2c(self._h, a, b, float(scale),
-                                        int(weighted), _stream(self.device)),
-                   "gfft_exec_z_r2c")
+        self._exec(_lib.gfft_exec_z_r2c, a, b, float(scale), int(weighted))
         return out
 
     def y_c2c(self, data, sign: int):
         a = self._check(data, self.cdtype, self._ncplx(), "data")
-        _lib.check(_lib.gfft_exec_y_c2c(self._h, a, int(sign),
-                                        _stream(self.device)), "gfft_exec_y_c2c")
+        self._exec(_lib.gfft_exec_y_c2c, a, int(sign))
         return data
 
     def z_c2r(self, g, out=None, scale: float = 1.0, weighted: bool = False):
         out = self.empty_real() if out is None else out
         a = self._check(g, self.cdtype, self._ncplx(), "input")
         b = self._check(out, self.dtype, self._nreal(), "output")
-        _lib.check(_lib.gfft_exec_z_c2r(self._h, a, b, float(scale),
-                                        int(weighted), _stream(self.device)),
-                   "gfft_exec_z_c2r")
+        self._exec(_lib.gfft_exec_z_c2r, a, b, float(scale), int(weighted))
         return out
 
     # ------------------------------------------------------------ lifetime
@@ -274,7 +269,7 @@ class Plan:
             pass
 
 
-class PencilPlan:
+class PencilPlan(_Exec):
     """Rank (r, c)'s share of an N^3 real FFT on a pr x pc pencil grid.
 
     Real pencil [batch, X, Y, N] (X = N/pr, Y = N/pc, z fastest).  The z pass
@@ -302,7 +297,7 @@ class PencilPlan:
         self.pr, self.pc = (int(v) for v in grid)
         self.col = int(col)
         self.batch = int(batch)
-        self.device = torch.device(device if device is not None else "cuda")
+        self.device = _resolve(device)
         if int(mfma_terms) not in (0, 2, 3):
             raise ValueError("mfma_terms must be 0, 2 or 3")
         flags = {0: 0, 2: _lib.GFFT_MFMA_BF16X2, 3: _lib.GFFT_MFMA_BF16X3}[int(mfma_terms)]
@@ -357,8 +352,7 @@ class PencilPlan:
                if out is None else out)
         a = self._check(ypencil, self.cdtype, self._n(self.ypencil_shape), "y-pencil")
         b = self._check(out, self.cdtype, self._n(self.send2_shape), "send")
-        _lib.check(_lib.gfft_pack_slab_for_alltoall(self._h, a, b, _stream(self.device)),
-                   "gfft_pack_slab_for_alltoall")
+        self._exec(_lib.gfft_pack_slab_for_alltoall, a, b)
         return out
 
     def unpack2(self, send, out=None):
@@ -367,8 +361,7 @@ class PencilPlan:
                if out is None else out)
         a = self._check(send, self.cdtype, self._n(self.send2_shape), "send")
         b = self._check(out, self.cdtype, self._n(self.ypencil_shape), "y-pencil")
-        _lib.check(_lib.gfft_unpack_slab_from_alltoall(self._h, a, b, _stream(self.device)),
-                   "gfft_unpack_slab_from_alltoall")
+        self._exec(_lib.gfft_unpack_slab_from_alltoall, a, b)
         return out
 
     def chunk(self, send: torch.Tensor, c: int) -> torch.Tensor:
@@ -388,20 +381,17 @@ class PencilPlan:
                if out is None else out)
         a = self._check(x, self.dtype, self._n(self.real_shape), "input")
         b = self._check(out, self.cdtype, self._n(self.send_shape), "output")
-        _lib.check(_lib.gfft_exec_z_r2c(self._h, a, b, float(scale), int(weighted),
-                                        _stream(self.device)), "gfft_exec_z_r2c")
+        self._exec(_lib.gfft_exec_z_r2c, a, b, float(scale), int(weighted))
         return out
 
     def y_c2c(self, ypencil, sign: int):
         a = self._check(ypencil, self.cdtype, self._n(self.ypencil_shape), "y-pencil")
-        _lib.check(_lib.gfft_exec_y_c2c(self._h, a, int(sign), _stream(self.device)),
-                   "gfft_exec_y_c2c")
+        self._exec(_lib.gfft_exec_y_c2c, a, int(sign))
         return ypencil
 
     def x_c2c(self, xpencil, sign: int):
         a = self._check(xpencil, self.cdtype, self._n(self.xpencil_shape), "x-pencil")
-        _lib.check(_lib.gfft_exec_x_c2c(self._h, a, int(sign), _stream(self.device)),
-                   "gfft_exec_x_c2c")
+        self._exec(_lib.gfft_exec_x_c2c, a, int(sign))
         return xpencil
 
     def z_c2r(self, g, out=None, scale: float = 1.0, weighted: bool = False):
@@ -410,8 +400,7 @@ class PencilPlan:
                if out is None else out)
         a = self._check(g, self.cdtype, self._n(self.send_shape), "input")
         b = self._check(out, self.dtype, self._n(self.real_shape), "output")
-        _lib.check(_lib.gfft_exec_z_c2r(self._h, a, b, float(scale), int(weighted),
-                                        _stream(self.device)), "gfft_exec_z_c2r")
+        self._exec(_lib.gfft_exec_z_c2r, a, b, float(scale), int(weighted))
         return out
 
     close = Plan.close

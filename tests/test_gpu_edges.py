@@ -47,6 +47,20 @@ def test_exec_rejects_bad_pointers_and_arguments():
         Plan(48, torch.float64)
 
 
+def test_plan_device_fixed_at_creation():
+    # a plan made without a device belongs to the device current at creation;
+    # its calls run with that device current, on its current stream
+    p = Plan(16, torch.float64)
+    assert p.device == torch.device("cuda", torch.cuda.current_device())
+    x = torch.zeros(p.real_shape, dtype=torch.float64, device="cuda")
+    x[0, 0, 0, 0] = 1.0
+    F = p.r2c(x)
+    torch.cuda.synchronize()
+    assert torch.equal(F, torch.ones_like(F))      # transform of a delta at the origin
+    with pytest.raises(ValueError):
+        p.r2c(x.cpu())
+
+
 def test_plan_query_sizes():
     p = Plan(64, torch.float32, slab_x=16, batch=3)
     sz = p.sizes

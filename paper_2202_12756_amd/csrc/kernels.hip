@@ -518,8 +518,11 @@ __global__ __launch_bounds__(kThreads) void k_pack_rows(
 }
 
 // ---------------------------------------------------------------- launchers
-// Grids are one-dimensional; refuse block counts a dim3 cannot hold.
-constexpr int64_t kMaxBlocks = 0x7fffffff;
+// Grids are one-dimensional, and a dispatch carries its size in work-items
+// as a 32-bit count: refuse grids beyond either limit.
+static bool grid_fits(int64_t blocks, int64_t threads) {
+    return blocks <= 0x7fffffff && blocks * threads <= int64_t(0xffffffff);
+}
 
 template <typename T, int N>
 static hipError_t z_r2c_n(const void* in, void* out, const void* tw, int64_t rows,
@@ -528,7 +531,7 @@ static hipError_t z_r2c_n(const void* in, void* out, const void* tw, int64_t row
     using Z = zshape<N / 2, C::EMAX, C::THREADS>;
     const int64_t blocks = (rows + Z::RPB - 1) / Z::RPB;
     if (blocks == 0) return hipSuccess;
-    if (blocks > kMaxBlocks) return hipErrorInvalidValue;
+    if (!grid_fits(blocks, Z::NT)) return hipErrorInvalidValue;
     if (map.pencil)
         hipLaunchKernelGGL((k_z_r2c_pencil<T, N, C::EMAX, C::THREADS, C::REMAP>), dim3(blocks),
                            dim3(Z::NT), 0, s, static_cast<const T*>(in), static_cast<cx<T>*>(out),
@@ -552,7 +555,7 @@ static hipError_t z_c2r_n(const void* in, void* out, const void* tw, int64_t row
     using Z = zshape<N / 2, C::EMAX, C::THREADS>;
     const int64_t blocks = (rows + Z::RPB - 1) / Z::RPB;
     if (blocks == 0) return hipSuccess;
-    if (blocks > kMaxBlocks) return hipErrorInvalidValue;
+    if (!grid_fits(blocks, Z::NT)) return hipErrorInvalidValue;
     if (map.pencil)
         hipLaunchKernelGGL((k_z_c2r_pencil<T, N, C::EMAX, C::THREADS, C::REMAP, C::NTS>),
                            dim3(blocks), dim3(Z::NT), 0, s, static_cast<const cx<T>*>(in),
@@ -586,7 +589,7 @@ static hipError_t strided_ax(int sign, void* data, const void* tw, int64_t m_col
     const int64_t tiles_m = (m_cols + TC - 1) / TC;
     const int64_t blocks = tiles_m * n_b;
     if (blocks == 0) return hipSuccess;
-    if (blocks > kMaxBlocks) return hipErrorInvalidValue;
+    if (!grid_fits(blocks, TC * SH::TPT)) return hipErrorInvalidValue;
     const dim3 threads(TC * SH::TPT);
     // x lines stream through non-temporally when every tile owns whole
     // 128-byte lines: at 1024^3 2% faster in FP64 and 4% in FP32, at 2048^3
@@ -673,10 +676,14 @@ hipError_t launch_pack(bool f64, const void* src, void* dst, int64_t chunks, int
                        hipStream_t s) {
     const int64_t len = y * k;
     int64_t bpc = (len + kThreads * 4 - 1) / (kThreads * 4);
+    // k_pack strides over its chunk, so fewer blocks per chunk keep very
+    // large grids within the dispatch's 32-bit work-item count
+    const int64_t cap = chunks > 0 ? int64_t(0xffffffff) / (chunks * kThreads) : 1;
+    if (bpc > cap) bpc = cap;
     if (bpc < 1) bpc = 1;
     const int64_t blocks = chunks * bpc;
     if (blocks == 0 || len == 0) return hipSuccess;
-    if (blocks > kMaxBlocks) return hipErrorInvalidValue;
+    if (!grid_fits(blocks, kThreads)) return hipErrorInvalidValue;
     if (f64)
         hipLaunchKernelGGL((k_pack<double>), dim3(blocks), dim3(kThreads), 0, s,
                            static_cast<const cx<double>*>(src), static_cast<cx<double>*>(dst),
@@ -692,7 +699,7 @@ hipError_t launch_pack_rows(bool f64, const void* src, void* dst, int64_t rows, 
                             row_map map, bool to_send, hipStream_t s) {
     const int64_t blocks = (rows + kPackRows - 1) / kPackRows;
     if (blocks == 0 || k == 0) return hipSuccess;
-    if (blocks > kMaxBlocks) return hipErrorInvalidValue;
+    if (!grid_fits(blocks, kThreads)) return hipErrorInvalidValue;
     if (f64)
         hipLaunchKernelGGL((k_pack_rows<double>), dim3(blocks), dim3(kThreads), 0, s,
                            static_cast<const cx<double>*>(src), static_cast<cx<double>*>(dst),

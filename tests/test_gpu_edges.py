@@ -1,5 +1,5 @@
 """Error paths that need a live plan, degenerate inputs, and the largest full
-grid one GPU holds (2048^3 FP64, 137 GB), checked by closed forms."""
+grids one GPU holds (2048^3 FP64, 137 GB; 2048^3 FP32), checked by closed forms."""
 import math
 
 import numpy as np
@@ -119,44 +119,54 @@ def _plane_wave(n, k0, out):
         out[0, x0:x0 + 64] = torch.cos(ph * (2 * math.pi / n)).to(out.dtype)
 
 
-@pytest.mark.parametrize("n", [1024, 2048])
-def test_largest_full_grid_closed_forms(n):
+# tolerances: peak error and off-peak residual relative to the peak N^3/2,
+# Parseval's relative mismatch, round-trip relative L2
+_CLOSED_TOL = {torch.float64: (1e-12, 1e-13, 1e-12, 1e-13),
+               torch.float32: (5e-6, 5e-6, 1e-5, 5e-6)}
+
+
+@pytest.mark.parametrize("n,dtype", [(1024, torch.float64), (2048, torch.float64),
+                                     (2048, torch.float32)], ids=["1024-f64", "2048-f64", "2048-f32"])
+def test_largest_full_grid_closed_forms(n, dtype):
     """The largest full grids one GPU holds (2048^3 FP64: 137 GB of buffers),
     checked without a host oracle: a plane wave's exact spectrum (N^3/2 at k0,
     nothing elsewhere in the stored half), then Parseval and the round trip
-    on a seeded field.  Reductions run in slabs to keep temporaries small."""
+    on a seeded field.  Reductions run in slabs, in FP64, to keep temporaries
+    small and the sums exact enough for the FP64 bounds."""
     import synth
 
+    t_peak, t_res, t_pars, t_rt = _CLOSED_TOL[dtype]
     k0 = (3, n - 5, 7)
-    p = Plan(n, torch.float64)
-    f = torch.empty(p.real_shape, dtype=torch.float64, device="cuda")
+    p = Plan(n, dtype)
+    f = torch.empty(p.real_shape, dtype=dtype, device="cuda")
     _plane_wave(n, k0, f)
     F = p.r2c(f)
-    peak = F[0, k0[0], k0[1], k0[2]].item()
-    assert abs(peak - n ** 3 / 2) <= 1e-12 * n ** 3
+    peak = complex(F[0, k0[0], k0[1], k0[2]].item())
+    assert abs(peak - n ** 3 / 2) <= t_peak * n ** 3 / 2
     F[0, k0[0], k0[1], k0[2]] = 0
-    resid = math.sqrt(sum(torch.sum(F[0, s:s + 64].abs() ** 2).item()
+    resid = math.sqrt(sum(torch.sum(F[0, s:s + 64].abs().double() ** 2).item()
                           for s in range(0, n, 64)))
-    print(f"{n}^3 FP64 plane wave: peak error {abs(peak - n ** 3 / 2):.3e}, "
+    print(f"{n}^3 {dtype} plane wave: peak error {abs(peak - n ** 3 / 2):.3e}, "
           f"residual / peak {resid / (n ** 3 / 2):.3e}")
-    assert resid <= 1e-13 * n ** 3 / 2
+    assert resid <= t_res * n ** 3 / 2
     # Parseval and the round trip on seeded uniform data
     for s in range(0, n, 128):
-        f[0, s:s + 128] = synth.uniform((128, n, n), 9, torch.float64, "cuda", offset=s * n * n)
+        f[0, s:s + 128] = synth.uniform((128, n, n), 9, dtype, "cuda", offset=s * n * n)
     p.r2c(f, F)
     w = torch.full((n // 2 + 1,), 2.0, dtype=torch.float64, device="cuda")
     w[0] = 1
     w[-1] = 1
-    e_phys = sum(torch.sum(f[0, s:s + 64] ** 2).item() for s in range(0, n, 64))
-    e_spec = sum(torch.sum(w * F[0, s:s + 64].abs() ** 2).item()
+    e_phys = sum(torch.sum(f[0, s:s + 64].double() ** 2).item() for s in range(0, n, 64))
+    e_spec = sum(torch.sum(w * F[0, s:s + 64].abs().double() ** 2).item()
                  for s in range(0, n, 64)) / n ** 3
-    assert abs(e_phys - e_spec) <= 1e-12 * e_phys
-    y = torch.empty_like(f)          # 2048^3: f, F and y hold 206 GB
+    assert abs(e_phys - e_spec) <= t_pars * e_phys
+    y = torch.empty_like(f)          # 2048^3 FP64: f, F and y hold 206 GB
     p.c2r(F, y, scale=1.0 / n ** 3)
-    num = sum(torch.sum((y[0, s:s + 64] - f[0, s:s + 64]) ** 2).item() for s in range(0, n, 64))
+    num = sum(torch.sum((y[0, s:s + 64].double() - f[0, s:s + 64].double()) ** 2).item()
+              for s in range(0, n, 64))
     rt = math.sqrt(num / e_phys)
-    print(f"{n}^3 FP64: Parseval rel {abs(e_phys - e_spec) / e_phys:.3e}, round trip {rt:.3e}")
-    assert rt <= 1e-13
+    print(f"{n}^3 {dtype}: Parseval rel {abs(e_phys - e_spec) / e_phys:.3e}, round trip {rt:.3e}")
+    assert rt <= t_rt
     del f, F, y, p
     torch.cuda.empty_cache()
 

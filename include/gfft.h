@@ -44,10 +44,20 @@ typedef enum {
     GFFT_E_ALIGN = -3,       /* a data pointer is not 16-byte aligned       */
     GFFT_E_NOMEM = -4,       /* plan tables could not be allocated          */
     GFFT_E_HIP = -5,         /* a HIP runtime call or kernel launch failed  */
-    GFFT_E_NO_DEVICE = -6    /* no usable gfx950 device is present          */
+    GFFT_E_NO_DEVICE = -6,   /* no usable gfx950 device is present          */
+    /* Not a status: widens the enumeration to every 32-bit value, so that
+     * any int a caller passes where a gfft_status is expected (for example
+     * to gfft_status_string) is a valid value of the type in C++ as in C. */
+    GFFT_STATUS_MAX_ENUM = 0x7fffffff
 } gfft_status;
 
-typedef enum { GFFT_F64 = 0, GFFT_F32 = 1 } gfft_dtype;
+typedef enum {
+    GFFT_F64 = 0,
+    GFFT_F32 = 1,
+    /* Not a type: makes every 32-bit value a valid gfft_dtype, so that a bad
+     * value reaches the argument check (GFFT_E_INVALID_ARG). */
+    GFFT_DTYPE_MAX_ENUM = 0x7fffffff
+} gfft_dtype;
 
 /* Plan flags. */
 enum {
@@ -290,6 +300,18 @@ gfft_status gfft_exec_y_c2c(const gfft_plan *plan, void *data, int sign,
 gfft_status gfft_exec_z_c2r(const gfft_plan *plan, const void *in_cplx,
                             void *out_real, double scale, int weighted,
                             void *stream);
+
+/*
+ * Plain device-to-device copy of `bytes` bytes (a multiple of 16; both
+ * pointers 16-byte aligned device pointers; the buffers must not overlap),
+ * one 16-byte element per work-item, enqueued on `stream`.  Not a step of
+ * the transform: it is the reference rate for contiguous HBM traffic
+ * against which the passes' bandwidth is judged (a pass that reads and
+ * writes B bytes cannot beat a copy of B/2 bytes).  A zero-byte copy does
+ * nothing.
+ */
+gfft_status gfft_device_copy(void *dst, const void *src, int64_t bytes,
+                             void *stream);
 
 /* Static description of a status code (never NULL). */
 const char *gfft_status_string(gfft_status status);

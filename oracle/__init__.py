@@ -36,6 +36,9 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "oracle.c")
 _LIB = os.path.join(_HERE, "liboracle.so")
+# ORACLE_LIB names another build of oracle.c (the sanitized build of the CPU
+# tests); by default the in-tree liboracle.so
+_LIB_OVERRIDE = os.environ.get("ORACLE_LIB")
 _lib = None
 
 DIRECT = 0
@@ -57,9 +60,10 @@ def build(force: bool = True) -> str:
 def _load():
     global _lib
     if _lib is None:
-        if not os.path.exists(_LIB):
+        path = _LIB_OVERRIDE or _LIB
+        if not _LIB_OVERRIDE and not os.path.exists(_LIB):
             build(force=True)
-        lib = ctypes.CDLL(_LIB)
+        lib = ctypes.CDLL(path)
         i64, dp, ip = ctypes.c_int64, ctypes.c_void_p, ctypes.c_int
         lib.oracle_c2c_axis.argtypes = [i64, i64, i64, dp, dp, ip, ip]
         lib.oracle_r2c_rows.argtypes = [i64, i64, dp, dp, ip]

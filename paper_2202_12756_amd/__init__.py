@@ -9,7 +9,7 @@ in hand-written HIP kernels for gfx950 behind the C ABI of include/gfft.h
 (``libgfft.so``); this package is its Python binding.
 """
 from ._lib import GfftError, load  # noqa: F401
-from .fft import Plan, PencilPlan  # noqa: F401
+from .fft import Plan, PencilPlan, device_copy  # noqa: F401
 from .autograd import RFFT3, IRFFT3, rfft3, irfft3  # noqa: F401
 
-__all__ = ["Plan", "PencilPlan", "GfftError", "load", "RFFT3", "IRFFT3", "rfft3", "irfft3"]
+__all__ = ["Plan", "PencilPlan", "device_copy", "GfftError", "load", "RFFT3", "IRFFT3", "rfft3", "irfft3"]

@@ -10,7 +10,9 @@ import ctypes
 import os
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libgfft.so")
+# GFFT_LIB names another build of the same sources (the host-sanitized build
+# of the CPU tests); by default the in-tree libgfft.so
+LIB_PATH = os.environ.get("GFFT_LIB") or os.path.join(HERE, "libgfft.so")
 
 GFFT_OK = 0
 GFFT_E_INVALID_ARG = -1
@@ -36,7 +38,7 @@ EXPORTS = (
     "gfft_exec_c2r_adjoint", "gfft_pack_slab_for_alltoall",
     "gfft_unpack_slab_from_alltoall", "gfft_exec_x_c2c",
     "gfft_exec_z_r2c", "gfft_exec_y_c2c", "gfft_exec_z_c2r",
-    "gfft_status_string", "gfft_version",
+    "gfft_device_copy", "gfft_status_string", "gfft_version",
 )
 
 
@@ -81,6 +83,7 @@ def load(path: str = LIB_PATH):
         "gfft_exec_z_r2c": [vp, vp, vp, dbl, i32, vp],
         "gfft_exec_y_c2c": [vp, vp, i32, vp],
         "gfft_exec_z_c2r": [vp, vp, vp, dbl, i32, vp],
+        "gfft_device_copy": [vp, vp, i64, vp],
         "gfft_status_string": [i32],
         "gfft_version": [],
     }
@@ -165,6 +168,10 @@ def gfft_exec_y_c2c(plan, data, sign, stream):
 
 def gfft_exec_z_c2r(plan, in_cplx, out_real, scale, weighted, stream):
     return load().gfft_exec_z_c2r(plan, in_cplx, out_real, scale, weighted, stream)
+
+
+def gfft_device_copy(dst, src, nbytes, stream):
+    return load().gfft_device_copy(dst, src, nbytes, stream)
 
 
 def gfft_status_string(status):

@@ -349,6 +349,7 @@ const char* gfft_status_string(gfft_status st) {
         case GFFT_E_NOMEM: return "out of device memory for plan tables";
         case GFFT_E_HIP: return "HIP runtime or kernel launch failure";
         case GFFT_E_NO_DEVICE: return "no usable gfx950 device";
+        case GFFT_STATUS_MAX_ENUM: break;
     }
     return "unknown status";
 }
@@ -589,6 +590,15 @@ gfft_status gfft_exec_z_c2r(const gfft_plan* p, const void* in, void* out, doubl
     if (!std::isfinite(scale)) return GFFT_E_INVALID_ARG;
     if ((st = check_device(p)) != GFFT_OK) return st;
     return run_z_c2r(p, in, out, scale, weighted != 0, as_stream(stream));
+}
+
+gfft_status gfft_device_copy(void* dst, const void* src, int64_t bytes, void* stream) {
+    if (bytes < 0 || bytes % 16 != 0) return GFFT_E_INVALID_ARG;
+    gfft_status st = check_ptr(src);
+    if (st != GFFT_OK || (st = check_ptr(dst)) != GFFT_OK) return st;
+    if (overlap(src, bytes, dst, bytes)) return GFFT_E_INVALID_ARG;
+    if (bytes == 0) return GFFT_OK;
+    return hip_status(gfft::launch_copy16(src, dst, bytes / 16, as_stream(stream)));
 }
 
 }  // extern "C"

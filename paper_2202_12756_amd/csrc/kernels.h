@@ -64,4 +64,7 @@ hipError_t launch_pack(bool f64, const void* src, void* dst, int64_t chunks,
 hipError_t launch_pack_rows(bool f64, const void* src, void* dst, int64_t rows, int64_t k,
                             row_map map, bool to_send, hipStream_t s);
 
+// Copy n16 16-byte elements from src to dst (one per work-item).
+hipError_t launch_copy16(const void* src, void* dst, int64_t n16, hipStream_t s);
+
 }  // namespace gfft

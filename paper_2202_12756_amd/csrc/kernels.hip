@@ -517,6 +517,15 @@ __global__ __launch_bounds__(kThreads) void k_pack_rows(
     }
 }
 
+// ---------------------------------------------------------------- copy
+// Plain streaming copy, one 16-byte element per work-item and no reuse: the
+// reference rate for what any pass can reach on contiguous memory.
+__global__ __launch_bounds__(kThreads) void k_copy16(const uint4* __restrict__ src,
+                                                     uint4* __restrict__ dst, int64_t n) {
+    const int64_t i = int64_t(blockIdx.x) * kThreads + threadIdx.x;
+    if (i < n) dst[i] = src[i];
+}
+
 // ---------------------------------------------------------------- launchers
 // Grids are one-dimensional, and a dispatch carries its size in work-items
 // as a 32-bit count: refuse grids beyond either limit.
@@ -709,6 +718,21 @@ hipError_t launch_pack_rows(bool f64, const void* src, void* dst, int64_t rows, 
                            static_cast<const cx<float>*>(src), static_cast<cx<float>*>(dst),
                            rows, k, map, to_send);
     return hipGetLastError();
+}
+
+hipError_t launch_copy16(const void* src, void* dst, int64_t n16, hipStream_t s) {
+    // at most 2^31 work-items per dispatch; longer copies take several
+    constexpr int64_t kMax = int64_t(1) << 31;
+    for (int64_t done = 0; done < n16; done += kMax) {
+        const int64_t len = n16 - done < kMax ? n16 - done : kMax;
+        const int64_t blocks = (len + kThreads - 1) / kThreads;
+        hipLaunchKernelGGL(k_copy16, dim3(blocks), dim3(kThreads), 0, s,
+                           static_cast<const uint4*>(src) + done, static_cast<uint4*>(dst) + done,
+                           len);
+        const hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
 }
 
 }  // namespace gfft

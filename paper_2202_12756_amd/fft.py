@@ -26,6 +26,24 @@ def _resolve(device) -> torch.device:
     return dev
 
 
+def device_copy(dst: torch.Tensor, src: torch.Tensor) -> torch.Tensor:
+    """Copy ``src`` into ``dst`` (same byte size, both contiguous on one GPU)
+    with the library's streaming copy kernel, on the current torch stream."""
+    if not (isinstance(dst, torch.Tensor) and isinstance(src, torch.Tensor)):
+        raise TypeError("dst and src must be torch.Tensors")
+    if dst.device != src.device or dst.device.type != "cuda":
+        raise ValueError("dst and src must live on the same GPU")
+    if not (dst.is_contiguous() and src.is_contiguous()):
+        raise ValueError("dst and src must be contiguous")
+    nbytes = src.numel() * src.element_size()
+    if dst.numel() * dst.element_size() != nbytes:
+        raise ValueError("dst and src must have the same byte size")
+    with torch.cuda.device(dst.device):
+        _lib.check(_lib.gfft_device_copy(dst.data_ptr(), src.data_ptr(), nbytes,
+                                         _stream(dst.device)), "gfft_device_copy")
+    return dst
+
+
 class _Exec:
     def _exec(self, fn, *args):
         """Call a library entry point with the plan's device current, on that

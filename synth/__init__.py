@@ -121,3 +121,18 @@ def paper_test_field(n: int) -> np.ndarray:
     sx, sy, sz = x[:, None, None], x[None, :, None], x[None, None, :]
     return (8.0 * np.sin(sx) * np.sin(2 * sy) * np.sin(3 * sz)
             + 8.0 * np.sin(4 * sx) * np.sin(5 * sy) * np.sin(6 * sz))
+
+
+def paper_test_field_torch(n: int, dtype=torch.float64, device="cpu") -> torch.Tensor:
+    """The same field built with torch on ``device`` (large grids on the GPU):
+    [1, N, N, N], the sines evaluated once per axis and combined by
+    broadcasting.  Values agree with ``paper_test_field`` to rounding."""
+    t = 2.0 * math.pi * torch.arange(n, dtype=torch.float64, device=device) / n
+    s = [torch.sin(a * t) for a in (1, 2, 3, 4, 5, 6)]
+    out = torch.empty((1, n, n, n), dtype=dtype, device=device)
+    for i0 in range(0, n, 64):
+        sl = slice(i0, min(n, i0 + 64))
+        blk = (8.0 * s[0][sl, None, None] * s[1][None, :, None] * s[2][None, None, :]
+               + 8.0 * s[3][sl, None, None] * s[4][None, :, None] * s[5][None, None, :])
+        out[0, sl] = blk.to(dtype)
+    return out

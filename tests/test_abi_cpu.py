@@ -131,6 +131,17 @@ def test_null_plan_and_out_pointer():
         assert fn(None, *extra) == _lib.GFFT_E_INVALID_ARG
 
 
+def test_device_copy_validates_on_host():
+    """Every argument check of the copy runs before any HIP call."""
+    assert _lib.gfft_device_copy(None, 4096, 64, None) == _lib.GFFT_E_INVALID_ARG
+    assert _lib.gfft_device_copy(4096, None, 64, None) == _lib.GFFT_E_INVALID_ARG
+    assert _lib.gfft_device_copy(4096, 8192, 24, None) == _lib.GFFT_E_INVALID_ARG   # not 16 x k
+    assert _lib.gfft_device_copy(4096, 8192, -16, None) == _lib.GFFT_E_INVALID_ARG
+    assert _lib.gfft_device_copy(4104, 8192, 64, None) == _lib.GFFT_E_ALIGN
+    assert _lib.gfft_device_copy(4096, 4096 + 32, 64, None) == _lib.GFFT_E_INVALID_ARG  # overlap
+    assert _lib.gfft_device_copy(4096, 8192, 0, None) == _lib.GFFT_OK                # nothing to do
+
+
 def _has_gpu():
     try:
         import torch

@@ -36,8 +36,27 @@ def test_recorded_traffic_requires_matching_sources(tmp_path):
 
 def test_only_groups():
     # every group --only offers is one of the variant functions of the full run
-    assert set(bench.ONLY) == {"slab_4096", "pencil_4096", "full_2048", "graphs"}
+    assert set(bench.ONLY) == {"slab_4096", "pencil_4096", "full_2048", "graphs",
+                               "kolmogorov_512", "losses_8x256"}
     assert all(callable(f) for f in bench.ONLY.values())
     r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--only", "nope"],
                        capture_output=True, text=True, timeout=120)
     assert r.returncode == 2 and "invalid choice" in r.stderr
+
+
+def test_cpu_model_and_hermitian_part():
+    import torch
+
+    assert isinstance(bench.cpu_model(), str) and bench.cpu_model()
+    # H(G) keeps interior bins, and on the kz = 0 and N/2 planes averages
+    # each bin with the conjugate of its mirror -k
+    n = 8
+    g = torch.complex(torch.randn(1, n, n, n // 2 + 1, dtype=torch.float64),
+                      torch.randn(1, n, n, n // 2 + 1, dtype=torch.float64))
+    h = bench._hermitian_part(g)
+    assert torch.equal(h[..., 1:-1], g[..., 1:-1])
+    for kz in (0, n // 2):
+        for i in range(n):
+            for j in range(n):
+                want = 0.5 * (g[0, i, j, kz] + g[0, (-i) % n, (-j) % n, kz].conj())
+                assert abs(h[0, i, j, kz] - want) < 1e-15

@@ -192,3 +192,19 @@ def test_line_alignment_paths_agree(dtype):
     y2 = p.c2r(F2, scale=1.0 / n ** 3)
     torch.cuda.synchronize()
     assert torch.equal(y1, y2)
+
+
+@pytest.mark.parametrize("nbytes", [16, 4096, 16 * 1000003, (1 << 28) + 48])
+def test_device_copy_is_bit_exact(nbytes):
+    """The bandwidth yardstick copies every byte (ragged lengths included) and
+    nothing past the end."""
+    from paper_2202_12756_amd import device_copy
+
+    src = torch.randint(-2 ** 62, 2 ** 62, (nbytes // 8,), dtype=torch.int64, device="cuda")
+    dst = torch.full((nbytes // 8 + 2,), -1, dtype=torch.int64, device="cuda")
+    device_copy(dst[: nbytes // 8], src)
+    torch.cuda.synchronize()
+    assert torch.equal(dst[: nbytes // 8], src)
+    assert torch.equal(dst[nbytes // 8:], torch.full((2,), -1, dtype=torch.int64, device="cuda"))
+    with pytest.raises(ValueError):
+        device_copy(dst[:3], src)

@@ -125,7 +125,7 @@ def test_paper_field_round_trip(n):
 
 
 @pytest.mark.parametrize("terms,bound", [(2, 1e-4), (3, 5e-6)])
-@pytest.mark.parametrize("n", [32, 64, 256, 1024])
+@pytest.mark.parametrize("n", [32, 64, 256, 1024, 2048, 4096])
 @pytest.mark.parametrize("sign", [-1, 1])
 def test_mfma_split_bf16_strided(n, terms, bound, sign):
     """First radix-16 stage on the matrix cores: error against the FP64

@@ -73,15 +73,17 @@ def recorded_traffic(path: str, pass_name: str):
     or None when the summary is missing or the kernels changed since."""
     if not os.path.exists(path):
         return None
-    sha, rows = None, {}
+    sha, rows, col = None, {}, None
     with open(path) as fh:
         for line in fh:
+            cells = [c.strip() for c in line.strip().strip("|").split("|")]
             if line.startswith("kernel_source_sha256_16:"):
                 sha = line.split(":", 1)[1].strip()
-            elif line.startswith("| ") and not line.startswith("| pass"):
-                cells = [c.strip() for c in line.strip().strip("|").split("|")]
-                if len(cells) >= 5 and cells[4].isdigit():
-                    rows[cells[0]] = int(cells[4])
+            elif line.startswith("| pass"):
+                col = cells.index("HBM bytes (scaled)") if "HBM bytes (scaled)" in cells else None
+            elif line.startswith("| ") and col is not None and len(cells) > col \
+                    and cells[col].isdigit():
+                rows[cells[0]] = int(cells[col])
     if sha != kernel_source_hash():
         return None
     return rows.get(pass_name)
@@ -244,29 +246,7 @@ def variants(n: int, steps: int, x64: torch.Tensor, dev) -> dict:
         torch.cuda.empty_cache()
     del x32, F64
     torch.cuda.empty_cache()
-    # the slab transpose of steps 2-4 at p = 8 (X = N/8 planes): the standalone
-    # pack, and step 1 with and without the pack fused into its stores
-    ranks = 8
-    ps = Plan(n, torch.float64, slab_x=n // ranks, device=dev)
-    pf = Plan(n, torch.float64, slab_x=n // ranks, fuse_pack=True, device=dev)
-    xs = x64[0, : n // ranks].contiguous()
-    S = ps.r2c(xs)
-    send = torch.empty(ps.send_shape, dtype=torch.complex128, device=dev)
-    ms_pack = time_pairs(lambda: ps.pack(S, send), steps, 2)
-    ms_unfused = time_pairs(lambda: (ps.r2c(xs, S), ps.pack(S, send)), steps, 2)
-    send2 = torch.empty_like(send)
-    ms_fused = time_pairs(lambda: pf.r2c(xs, send2), steps, 2)
-    cs = S.numel() * 16
-    out["slab_pack_p8_f64"] = {
-        "chunk": f"{n // ranks}x{n // ranks}x{k}",
-        "pack_ms": round(ms_pack, 4),
-        "pack_GBps": round(2 * cs / (ms_pack * 1e-3) / 1e9, 1),
-        "r2c2d_then_pack_ms": round(ms_unfused, 4),
-        "r2c2d_fused_pack_ms": round(ms_fused, 4),
-        "fused_equals_standalone": bool(torch.equal(send, send2)),
-    }
-    del ps, pf, xs, S, send, send2
-    torch.cuda.empty_cache()
+    out.update(slab_pack_p8(steps, dev, x64 if n == 1024 else None))
     # adjoint pair in FP64
     G = p64.empty_spectrum()
     h = p64.empty_real()
@@ -285,6 +265,43 @@ def variants(n: int, steps: int, x64: torch.Tensor, dev) -> dict:
     out.update(pencil_variants(steps, dev))
     out.update(graph_variants(steps, dev))
     out.update(full_grid_2048(steps, dev))
+    return out
+
+
+def slab_pack_p8(steps: int, dev, x64: torch.Tensor | None = None) -> dict:
+    """The slab transpose of the paper's steps 2-4 at p = 8 on the 1024^3 FP64
+    grid (rank 0: X = 128 planes, chunks of 128 x 128 x 513): the standalone
+    pack into the 8 send chunks, and the local 2D R2C (step 1) with and
+    without the pack fused into the z pass's stores (send buffers compared
+    bit for bit)."""
+    import synth
+    from paper_2202_12756_amd import Plan
+
+    n, ranks = 1024, 8
+    k = n // 2 + 1
+    ps = Plan(n, torch.float64, slab_x=n // ranks, device=dev)
+    pf = Plan(n, torch.float64, slab_x=n // ranks, fuse_pack=True, device=dev)
+    if x64 is not None:
+        xs = x64[0, : n // ranks].contiguous()
+    else:
+        xs = synth.uniform(ps.real_shape, 3, torch.float64, dev)
+    S = ps.r2c(xs)
+    send = torch.empty(ps.send_shape, dtype=torch.complex128, device=dev)
+    pack = time_stats(lambda: ps.pack(S, send), steps, 2)
+    unfused = time_stats(lambda: (ps.r2c(xs, S), ps.pack(S, send)), steps, 2)
+    send2 = torch.empty_like(send)
+    fused = time_stats(lambda: pf.r2c(xs, send2), steps, 2)
+    cs = S.numel() * 16
+    out = {"slab_pack_p8_f64": {
+        "chunk": f"{n // ranks}x{n // ranks}x{k}",
+        "pack_ms": pack["mean_ms"], "pack": pack,
+        "pack_GBps": round(2 * cs / (pack["median_ms"] * 1e-3) / 1e9, 1),
+        "r2c2d_then_pack_ms": unfused["mean_ms"], "r2c2d_then_pack": unfused,
+        "r2c2d_fused_pack_ms": fused["mean_ms"], "r2c2d_fused_pack": fused,
+        "fused_equals_standalone": bool(torch.equal(send, send2)),
+    }}
+    del ps, pf, xs, S, send, send2
+    torch.cuda.empty_cache()
     return out
 
 
@@ -626,7 +643,8 @@ def eq5_1024(plan, F, y, n: int, dev) -> dict:
 # workload groups that --only runs by themselves
 ONLY = {"slab_4096": slab_share_4096, "pencil_4096": pencil_variants,
         "full_2048": full_grid_2048, "graphs": graph_variants,
-        "kolmogorov_512": kolmogorov_512, "losses_8x256": losses_8x256}
+        "kolmogorov_512": kolmogorov_512, "losses_8x256": losses_8x256,
+        "slab_pack_p8": slab_pack_p8}
 
 
 def main():

@@ -37,7 +37,7 @@ def test_recorded_traffic_requires_matching_sources(tmp_path):
 def test_only_groups():
     # every group --only offers is one of the variant functions of the full run
     assert set(bench.ONLY) == {"slab_4096", "pencil_4096", "full_2048", "graphs",
-                               "kolmogorov_512", "losses_8x256"}
+                               "kolmogorov_512", "losses_8x256", "slab_pack_p8"}
     assert all(callable(f) for f in bench.ONLY.values())
     r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--only", "nope"],
                        capture_output=True, text=True, timeout=120)

@@ -155,6 +155,7 @@ def cpu_baseline(n: int, planes: int, seed: int, min_seconds: float = 10.0) -> d
         reps1, dt1, per_rep1 = _oracle_sample(n, one_planes, seed, min_seconds / 2, 20)
     finally:
         oracle.set_num_threads(threads)
+    slab = _oracle_slab_4096_sample(seed)
     return {"value": round(reps * per_rep / dt, 3), "unit": "GFLOP/s",
             "cores": threads, "kind": "oracle",
             "sample": (f"radix-2 FP64 oracle: 2D R2C+C2R on {planes} of {n} "
@@ -167,7 +168,34 @@ def cpu_baseline(n: int, planes: int, seed: int, min_seconds: float = 10.0) -> d
                          "sample": (f"the same sample on {one_planes} planes and a "
                                     f"[{n}][{one_planes}][{k}] pencil, one thread, "
                                     f"repeated {reps1}x"),
-                         "seconds": round(dt1, 3)}}
+                         "seconds": round(dt1, 3)},
+            "slab_4096_p64_f64": slab}
+
+
+def _oracle_slab_4096_sample(seed: int) -> dict:
+    """The 4096^3 / 64-rank slab share's forward work on the oracle, scaled:
+    the 2D R2C of one of the 64 x-planes and the x lines of one of the 64
+    y_l slices of the received pencil, each timed once on all threads and
+    multiplied by 64 (labelled as scaled)."""
+    import oracle
+    import synth
+
+    n, planes = 4096, 64
+    k = n // 2 + 1
+    f = synth.uniform((1, n, n), seed + 10, torch.float64).numpy()
+    pen = (synth.uniform((n, 1, k), seed + 11, torch.float64).numpy()
+           + 1j * synth.uniform((n, 1, k), seed + 12, torch.float64).numpy())
+    t0 = time.perf_counter()
+    oracle.r2c2d_planes(f)
+    t1 = time.perf_counter()
+    oracle.x_c2c(pen, -1)
+    t2 = time.perf_counter()
+    fwd = planes * ((t1 - t0) + (t2 - t1))
+    gflop = 5.0 * (n ** 3 / 2) * math.log2(n ** 3) / planes / 1e9
+    return {"scaled_forward_ms": round(fwd * 1e3, 1), "GFLOPs": round(gflop / fwd, 3),
+            "sample": (f"2D R2C of one 4096x4096 plane ({(t1 - t0) * 1e3:.1f} ms) and the x lines "
+                       f"of one [4096][1][2049] pencil slice ({(t2 - t1) * 1e3:.1f} ms), each x64 "
+                       f"(scaled, not run on the whole share)")}
 
 
 def time_pairs(fn, steps: int, warmup: int) -> float:

@@ -303,8 +303,9 @@ gfft_status gfft_exec_z_c2r(const gfft_plan *plan, const void *in_cplx,
 
 /*
  * Plain device-to-device copy of `bytes` bytes (a multiple of 16; both
- * pointers 16-byte aligned device pointers; the buffers must not overlap),
- * one 16-byte element per work-item, enqueued on `stream`.  Not a step of
+ * pointers 16-byte aligned, in memory the current device can access; the
+ * buffers must not overlap), one 16-byte element per work-item, enqueued on
+ * `stream` (a stream of the current device).  Not a step of
  * the transform: it is the reference rate for contiguous HBM traffic
  * against which the passes' bandwidth is judged (a pass that reads and
  * writes B bytes cannot beat a copy of B/2 bytes).  A zero-byte copy does

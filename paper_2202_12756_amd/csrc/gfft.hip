@@ -249,6 +249,21 @@ gfft_status check_r2c_args(const gfft_plan* p, const void* real, const void* cpl
     return GFFT_OK;
 }
 
+// Step 1 or its inverse as one pass per plane where a plane fits on a CU
+// and that is measured faster (FP32, N = 64..256; not for pencil plans,
+// whose z output is cut into kz chunks, nor with the matrix-core stage,
+// which belongs to the y pass).
+bool plane_pass(const gfft_plan* p, bool fwd) {
+    return !p->pencil && mfma_terms(p) == 0 && gfft::plane_supported(f64(p), int(p->n), fwd);
+}
+
+gfft_status run_plane(const gfft_plan* p, bool fwd, const void* in, void* out, double scale,
+                      bool weighted, hipStream_t s) {
+    const double me = scale, mi = weighted ? (fwd ? 2.0 : 0.5) * scale : scale;
+    return hip_status(gfft::launch_plane(f64(p), fwd, int(p->n), in, out, p->tw,
+                                         p->batch * p->x, zmap(p), me, mi, s));
+}
+
 gfft_status forward(const gfft_plan* p, const void* in, void* out, double scale,
                     bool weighted, void* stream) {
     gfft_status st = check_r2c_args(p, in, out);
@@ -257,8 +272,12 @@ gfft_status forward(const gfft_plan* p, const void* in, void* out, double scale,
     if (!std::isfinite(scale)) return GFFT_E_INVALID_ARG;
     if ((st = check_device(p)) != GFFT_OK) return st;
     hipStream_t s = as_stream(stream);
-    if ((st = run_z_r2c(p, in, out, scale, weighted, s)) != GFFT_OK) return st;
-    if ((st = run_y(p, out, -1, s)) != GFFT_OK) return st;
+    if (plane_pass(p, true)) {
+        if ((st = run_plane(p, true, in, out, scale, weighted, s)) != GFFT_OK) return st;
+    } else {
+        if ((st = run_z_r2c(p, in, out, scale, weighted, s)) != GFFT_OK) return st;
+        if ((st = run_y(p, out, -1, s)) != GFFT_OK) return st;
+    }
     if (p->p == 1) st = run_x(p, out, -1, s);
     return st;
 }
@@ -272,6 +291,7 @@ gfft_status inverse(const gfft_plan* p, void* in, void* out, double scale, bool 
     if ((st = check_device(p)) != GFFT_OK) return st;
     hipStream_t s = as_stream(stream);
     if (p->p == 1 && (st = run_x(p, in, +1, s)) != GFFT_OK) return st;
+    if (plane_pass(p, false)) return run_plane(p, false, in, out, scale, weighted, s);
     if ((st = run_y(p, in, +1, s)) != GFFT_OK) return st;
     return run_z_c2r(p, in, out, scale, weighted, s);
 }

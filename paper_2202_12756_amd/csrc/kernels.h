@@ -64,6 +64,17 @@ hipError_t launch_pack(bool f64, const void* src, void* dst, int64_t chunks,
 hipError_t launch_pack_rows(bool f64, const void* src, void* dst, int64_t rows, int64_t k,
                             row_map map, bool to_send, hipStream_t s);
 
+// Step 1 (z R2C and y C2C of every x-plane) in one pass, or its inverse
+// (y C2C, then z C2R), one plane per workgroup: FP32, N = 64 and 128 both
+// ways, N = 256 forward only (plane_supported).  Rows of the half spectrum
+// follow `map` as in the z passes; the bin multipliers are those of the z
+// passes.  `in` and `out` may be the same buffer (in-place plans): each
+// plane is read whole before any of it is written.
+bool plane_supported(bool f64, int n, bool forward);
+hipError_t launch_plane(bool f64, bool forward, int n, const void* in, void* out, const void* tw,
+                        int64_t planes, row_map map, double mul_edge, double mul_int,
+                        hipStream_t s);
+
 // Copy n16 16-byte elements from src to dst (one per work-item).
 hipError_t launch_copy16(const void* src, void* dst, int64_t n16, hipStream_t s);
 

@@ -91,19 +91,23 @@ struct zshape {
 // faster there), 32 per thread for N = 4096; FP64 C2R 16 per thread in
 // 64-thread workgroups; FP32 32 per thread, in 256-thread workgroups for the
 // R2C from N = 1024 up (4-10% faster with the radix-32 stages) and 64-thread
-// ones otherwise.
+// ones otherwise, except at N = 256 and 512: 16 per thread in 256-thread
+// workgroups (the C2R of N = 512 in 128-thread ones), 5-13% faster there.
 // Workgroups are dealt to XCDs in contiguous ranges by the C2R at every N
-// (3-5%) and by the R2C from N = 1024 up (2-3%).  The C2R also stores its
-// line-aligned
-// real rows non-temporally (they are not read again soon); the R2C's
-// complex rows are not line-aligned and gain nothing from it.
+// (3-5%) and by the R2C from N = 1024 up (2-3%) and at the FP32 N = 256 and
+// 512 shapes.  The C2R also stores its line-aligned real rows
+// non-temporally (they are not read again soon); the R2C's complex rows are
+// not line-aligned and gain nothing from it.
 template <typename T, bool FWD, int N>
 struct zcfg {
     static constexpr bool F64 = sizeof(T) == 8;
-    static constexpr int EMAX = F64 ? (FWD ? (N >= 4096 ? 32 : N >= 1024 ? 16 : 8) : 16) : 32;
+    static constexpr bool MID32 = !F64 && (N == 256 || N == 512);
+    static constexpr int EMAX =
+        F64 ? (FWD ? (N >= 4096 ? 32 : N >= 1024 ? 16 : 8) : 16) : (MID32 ? 16 : 32);
     static constexpr int THREADS =
-        F64 ? (FWD ? (N >= 1024 ? 128 : 256) : 64) : (FWD && N >= 1024 ? 256 : 64);
-    static constexpr bool REMAP = !FWD || N >= 1024;
+        F64 ? (FWD ? (N >= 1024 ? 128 : 256) : 64)
+            : MID32 ? (FWD || N == 256 ? 256 : 128) : (FWD && N >= 1024 ? 256 : 64);
+    static constexpr bool REMAP = !FWD || N >= 1024 || MID32;
     static constexpr bool NTS = !FWD;
 };
 
@@ -530,16 +534,22 @@ template <typename T, int N, int AX, bool MFMA = false>
 struct sshape {
     static constexpr bool F64 = sizeof(T) == 8;
     static constexpr bool WIDE = AX == 0 || N >= 2048;
-    static constexpr int E = MFMA ? 16 : N >= 512 ? 32 : 16;
+    // FP32 lines of N = 256 and x lines of N = 512: 32 columns (256-byte
+    // runs), 4% faster than 16 (at N = 256 the x tile with 32 elements per
+    // thread, the y tile with 16)
+    static constexpr bool C32 = !F64 && !MFMA && (N == 256 || (N == 512 && AX == 1));
+    static constexpr int E = MFMA ? 16 : (N >= 512 || (C32 && AX == 1)) ? 32 : 16;
     static constexpr int TPT = N / E;
     // FP32 y lines of N = 2048: two 8-column tiles per CU (9% faster than
-    // one 16-column tile)
+    // one 16-column tile); FP64 y lines of N = 512: two 16-column tiles with
+    // the split exchange (8% faster than one with whole values)
     static constexpr bool Y2048 = !F64 && !MFMA && AX == 0 && N == 2048;
+    static constexpr bool Y512 = F64 && AX == 0 && N == 512;
     static constexpr bool BIG32 = N >= 2048 && !Y2048;
     static constexpr int MAXT = F64 ? (WIDE ? 512 : 256) : (BIG32 || MFMA ? 1024 : 512);
-    static constexpr int LDS = (F64 ? WIDE : BIG32) ? 131072 : 65536;
+    static constexpr int LDS = (F64 ? WIDE && !Y512 : BIG32) ? 131072 : 65536;
     static constexpr int TC_T = MAXT / TPT;
-    static constexpr int CAP = (256 / TPT) > 16 ? (256 / TPT) : 16;
+    static constexpr int CAP = C32 ? 32 : (256 / TPT) > 16 ? (256 / TPT) : 16;
     static constexpr int FULL = LDS / (N * int(sizeof(cx<T>)));
     static constexpr int A0 = TC_T < CAP ? TC_T : CAP;
     static constexpr int A1 = A0 < 2 * FULL ? A0 : 2 * FULL;
@@ -819,11 +829,11 @@ static hipError_t strided_ax(int sign, void* data, const void* tw, int64_t m_col
     // x lines stream through non-temporally when every tile owns whole
     // 128-byte lines: at 1024^3 2% faster in FP64 and 4% in FP32, at 2048^3
     // 8% faster in FP32 but 5% slower in FP64 (one 512-thread workgroup per
-    // CU), so FP64 uses it for N = 512 and 1024 only.  Where neighbouring
-    // tiles share lines, as in the y passes, the hint makes them travel twice
-    // (15-50% slower).
-    if constexpr (AX == 1 && MF == 0 && N >= 512 && (sizeof(T) == 4 || N <= 1024) &&
-                  (TC * sizeof(cx<T>)) % 128 == 0) {
+    // CU), so FP64 uses it for N = 512 and 1024 only, FP32 from N = 256.
+    // Where neighbouring tiles share lines, as in the y passes, the hint
+    // makes them travel twice (15-50% slower).
+    if constexpr (AX == 1 && MF == 0 && (N >= 512 || (sizeof(T) == 4 && N == 256)) &&
+                  (sizeof(T) == 4 || N <= 1024) && (TC * sizeof(cx<T>)) % 128 == 0) {
         if (whole_lines(data, m_cols, lm, 128 / int64_t(sizeof(cx<T>)))) {
             if (sign < 0)
                 hipLaunchKernelGGL((k_strided<T, N, TC, SH::XP, -1, SH::E, 0, true>), dim3(blocks),

@@ -13,7 +13,7 @@ from paper_2202_12756_amd import GfftError, PencilPlan, _lib
 pytestmark = pytest.mark.gpu
 
 CASES = [(16, 2, 4), (32, 4, 8), (32, 8, 16), (64, 2, 2), (64, 4, 16), (128, 4, 4),
-         (32, 8, 2), (32, 32, 16), (128, 16, 4)]
+         (32, 8, 2), (32, 32, 16), (128, 16, 4), (256, 4, 8)]
 
 
 def _plans(n, pr, pc, dtype, batch=1, mfma_terms=0):
@@ -234,6 +234,19 @@ def test_pencil_batched_y_and_x_passes(grid):
             send = p.pack2(yp)
             torch.cuda.synchronize()
             assert np.array_equal(host(send), oracle.pencil_pack2(host(yp), p.h))
+
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32], ids=["f64", "f32"])
+@pytest.mark.parametrize("col", [0, 3])
+def test_pencil_512_y_pass(dtype, col):
+    """N = 512 y pencils (the FP32 tile of 16 columns, the FP64 tile with the
+    split exchange), kz widths 64 and 65 (ragged last tile)."""
+    n, pr, pc = 512, 2, 4
+    p = PencilPlan(n, dtype, (pr, pc), col)
+    yp, ypref = cplx_input(p.ypencil_shape, 1700 + col, dtype)
+    p.y_c2c(yp, -1)
+    torch.cuda.synchronize()
+    assert rel_l2(host(yp)[0], oracle.pencil_y_c2c(ypref[0], -1)) <= TOL[dtype]
 
 
 @pytest.mark.parametrize("dtype", [torch.float64, torch.float32], ids=["f64", "f32"])

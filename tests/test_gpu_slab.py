@@ -84,7 +84,8 @@ def test_virtual_ranks_match_full_grid(n, p, dtype):
 
 
 @pytest.mark.parametrize("dtype", [torch.float64, torch.float32], ids=["f64", "f32"])
-@pytest.mark.parametrize("n,x,batch", [(16, 16, 1), (64, 64, 2), (128, 32, 1), (1024, 2, 1)])
+@pytest.mark.parametrize("n,x,batch", [(16, 16, 1), (64, 64, 2), (128, 32, 1), (512, 2, 1),
+                                         (1024, 2, 1)])
 def test_inplace_padded_layout(n, x, batch, dtype):
     """FFTW-padded in-place R2C/C2R in one shared buffer (rows of N + 2)."""
     p = Plan(n, dtype, slab_x=x, batch=batch, inplace=True)

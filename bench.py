@@ -7,7 +7,9 @@ resident in HBM.  `value` is the wall-clock rate of those K steps; HIP events
 around each step give its median and minimum.  An instrumented repeat of the
 same K steps through the single-pass entry points, with HIP events between
 the passes on the launch stream, gives each kernel's live duration (the
-roofline figure).
+roofline figure).  Two yardsticks sit beside it: the library's streaming
+copy (contiguous traffic) and the y and x passes' loads and stores without
+their transform (the ceiling of their access pattern).
 
 Prints ONE JSON line (rank 0).  Run ``python bench.py --help`` for options.
 """
@@ -213,6 +215,17 @@ def time_pairs(fn, steps: int, warmup: int) -> float:
     return a.elapsed_time(b) / steps
 
 
+def pattern_copies(plan, ydata, xdata, nbytes: int, steps: int = 5) -> dict:
+    """GB/s of the y and x passes' loads and stores without their transform
+    (gfft_exec_pass_copy; the data end up conjugated an odd number of times),
+    nbytes read and written per launch."""
+    out = {}
+    for ax, key, data in ((0, "y", ydata), (1, "x", xdata)):
+        ms = time_pairs(lambda: plan.pass_copy(data, ax), steps, 1)
+        out[key] = round(nbytes / (ms * 1e-3) / 1e9, 1)
+    return out
+
+
 def time_stats(fn, steps: int, warmup: int) -> dict:
     """Per-call HIP-event times of fn() over `steps` calls (after `warmup`):
     mean, median and min in ms, events on the current stream."""
@@ -270,6 +283,8 @@ def variants(n: int, steps: int, x64: torch.Tensor, dev) -> dict:
                                                      / PEAK_HBM_GBS, 4),
                      "forward_rel_l2_vs_fp64_path": fwd_err,
                      "roundtrip_rel_l2_vs_fp64_input": rt}
+        if terms == 0:
+            out[name]["pattern_copy_GBps"] = pattern_copies(p32, F32, F32, 2 * C)
         del F32, y32, p32
         torch.cuda.empty_cache()
     del x32, F64
@@ -438,6 +453,7 @@ def slab_share_4096(steps: int, dev) -> dict:
         "real_slab": f"{X}x{n}x{n}", "send_blocks": f"{ranks}x{X}x{X}x{n // 2 + 1}",
         "pass_ms": {k: round(v, 4) for k, v in ms.items()},
         "pass_GBps": {k: round(bts[k] / (ms[k] * 1e-3) / 1e9, 1) for k in ms},
+        "pattern_copy_GBps": pattern_copies(p, send, pen, bts["y_fwd"]),
         "chain_ms": round(chain, 4),
         "chain_hbm_roofline_frac": round(sum(bts.values()) / (chain * 1e-3) / 1e9
                                          / PEAK_HBM_GBS, 4),
@@ -849,6 +865,13 @@ def main():
     line["roofline"]["frac_of_copy"] = round(gbs[dom] / line["copy_GBps"], 4)
     line["pair_frac_of_copy"] = round(model_bytes / (ms_step * 1e-3) / 1e9
                                       / line["copy_GBps"], 4)
+    # the strided passes' own access-pattern ceilings: their loads and stores
+    # without the transform (gfft_exec_pass_copy), on the same spectrum
+    line["pattern_copy_GBps"] = pattern_copies(plan, F, F, 2 * C)
+    if dom[0] in "yx":
+        ceil = line["pattern_copy_GBps"][dom[0]]
+        line["roofline"]["pattern_copy_GBps"] = ceil
+        line["roofline"]["frac_of_pattern_copy"] = round(gbs[dom] / ceil, 4)
     if not args.no_variants:
         del F, y
         torch.cuda.empty_cache()

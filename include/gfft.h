@@ -314,6 +314,22 @@ gfft_status gfft_exec_z_c2r(const gfft_plan *plan, const void *in_cplx,
 gfft_status gfft_device_copy(void *dst, const void *src, int64_t bytes,
                              void *stream);
 
+/*
+ * Access-pattern yardstick of a strided pass (not a step of the transform):
+ * reads and writes every element that gfft_exec_y_c2c (axis 0) or
+ * gfft_exec_x_c2c (axis 1) would, in place, with that pass's tile shape,
+ * workgroup order and memory hints, but runs no transform: each element is
+ * replaced by its complex conjugate.  Its rate is the ceiling of the pass's
+ * memory access pattern (the pass without its arithmetic and exchanges).
+ *   data : the buffer gfft_exec_y_c2c / gfft_exec_x_c2c takes on this plan
+ *          (same layout, size, alignment and device rules).
+ * Errors: GFFT_E_INVALID_ARG for a NULL plan or pointer, an axis other than
+ * 0 or 1, or a current device other than the plan's; GFFT_E_ALIGN;
+ * GFFT_E_HIP for a launch failure.
+ */
+gfft_status gfft_exec_pass_copy(const gfft_plan *plan, int axis, void *data,
+                                void *stream);
+
 /* Static description of a status code (never NULL). */
 const char *gfft_status_string(gfft_status status);
 

@@ -38,7 +38,7 @@ EXPORTS = (
     "gfft_exec_c2r_adjoint", "gfft_pack_slab_for_alltoall",
     "gfft_unpack_slab_from_alltoall", "gfft_exec_x_c2c",
     "gfft_exec_z_r2c", "gfft_exec_y_c2c", "gfft_exec_z_c2r",
-    "gfft_device_copy", "gfft_status_string", "gfft_version",
+    "gfft_device_copy", "gfft_exec_pass_copy", "gfft_status_string", "gfft_version",
 )
 
 
@@ -84,6 +84,7 @@ def load(path: str = LIB_PATH):
         "gfft_exec_y_c2c": [vp, vp, i32, vp],
         "gfft_exec_z_c2r": [vp, vp, vp, dbl, i32, vp],
         "gfft_device_copy": [vp, vp, i64, vp],
+        "gfft_exec_pass_copy": [vp, i32, vp, vp],
         "gfft_status_string": [i32],
         "gfft_version": [],
     }
@@ -172,6 +173,10 @@ def gfft_exec_z_c2r(plan, in_cplx, out_real, scale, weighted, stream):
 
 def gfft_device_copy(dst, src, nbytes, stream):
     return load().gfft_device_copy(dst, src, nbytes, stream)
+
+
+def gfft_exec_pass_copy(plan, axis, data, stream):
+    return load().gfft_exec_pass_copy(plan, axis, data, stream)
 
 
 def gfft_status_string(status):

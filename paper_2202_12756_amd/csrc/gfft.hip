@@ -220,21 +220,22 @@ int mfma_terms(const gfft_plan* p) {
     return 0;
 }
 
-gfft_status run_y(const gfft_plan* p, void* data, int sign, hipStream_t s) {
+// copy: the pass's loads and stores without its transform (gfft_exec_pass_copy)
+gfft_status run_y(const gfft_plan* p, void* data, int sign, hipStream_t s, bool copy = false) {
     const int64_t cols = p->pencil ? p->w : p->k;
-    return hip_status(gfft::launch_strided(f64(p), int(p->n), 0, mfma_terms(p), sign, data,
-                                           p->tw, cols, p->batch * p->x, ymap(p), s));
+    return hip_status(gfft::launch_strided(f64(p), int(p->n), 0, copy ? -1 : mfma_terms(p), sign,
+                                           data, p->tw, cols, p->batch * p->x, ymap(p), s));
 }
 
-gfft_status run_x(const gfft_plan* p, void* data, int sign, hipStream_t s) {
+gfft_status run_x(const gfft_plan* p, void* data, int sign, hipStream_t s, bool copy = false) {
     int64_t cols = paper(p) ? p->k : p->y * p->k;
     int64_t sets = paper(p) ? p->batch * p->y : p->batch;
     if (p->pencil) {
         cols = p->h > 1 ? (p->n / p->pr) * p->w : p->y * p->w;
         sets = p->h > 1 ? p->batch : p->batch * p->g;
     }
-    return hip_status(gfft::launch_strided(f64(p), int(p->n), 1, mfma_terms(p), sign, data,
-                                           p->tw, cols, sets, xmap(p), s));
+    return hip_status(gfft::launch_strided(f64(p), int(p->n), 1, copy ? -1 : mfma_terms(p), sign,
+                                           data, p->tw, cols, sets, xmap(p), s));
 }
 
 // `real` and `cplx` are the two buffers of a z pass: distinct and disjoint,
@@ -610,6 +611,15 @@ gfft_status gfft_exec_z_c2r(const gfft_plan* p, const void* in, void* out, doubl
     if (!std::isfinite(scale)) return GFFT_E_INVALID_ARG;
     if ((st = check_device(p)) != GFFT_OK) return st;
     return run_z_c2r(p, in, out, scale, weighted != 0, as_stream(stream));
+}
+
+gfft_status gfft_exec_pass_copy(const gfft_plan* p, int axis, void* data, void* stream) {
+    if (!p) return GFFT_E_INVALID_ARG;
+    if (axis != 0 && axis != 1) return GFFT_E_INVALID_ARG;
+    gfft_status st = check_ptr(data);
+    if (st != GFFT_OK || (st = check_device(p)) != GFFT_OK) return st;
+    return axis == 0 ? run_y(p, data, -1, as_stream(stream), true)
+                     : run_x(p, data, -1, as_stream(stream), true);
 }
 
 gfft_status gfft_device_copy(void* dst, const void* src, int64_t bytes, void* stream) {

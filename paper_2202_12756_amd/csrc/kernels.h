@@ -48,7 +48,9 @@ hipError_t launch_z_c2r(bool f64, int n, const void* in, void* out, const void* 
 // axis 0: y lines (short stride); axis 1: x lines (long stride).  Picks the
 // tile shape measured best for that stride.  mfma_terms 2 or 3 (FP32, N >= 32
 // only) runs the first radix-16 stage on the matrix cores with that many
-// BF16 terms per operand; 0 keeps every stage on the vector ALUs.
+// BF16 terms per operand; 0 keeps every stage on the vector ALUs; -1 runs
+// no transform but the vector pass's loads and stores, storing each element's
+// conjugate (sign ignored).
 hipError_t launch_strided(bool f64, int n, int axis, int mfma_terms, int sign, void* data,
                           const void* tw, int64_t m_cols, int64_t n_b, line_map lm,
                           hipStream_t s);

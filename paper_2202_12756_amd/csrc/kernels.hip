@@ -561,6 +561,9 @@ struct sshape {
 // imaginary parts; the LDS tile is N*TC/XP complex values (padded).
 // NT: non-temporal loads and stores of the lines (no reuse), for tilings in
 // which every 128-byte line belongs to one tile (the host checks this).
+// MF: 0 vector stages; 2 or 3 the first radix-16 stage on the matrix cores;
+// -1 no transform (each element replaced by its conjugate): the same loads
+// and stores as the pass, a yardstick for its memory-access ceiling.
 template <typename T, int N, int TC, int XP, int S, int E = 16, int MF = 0, bool NT = false>
 __global__ __launch_bounds__(TC * N / E) void k_strided(
     cx<T>* __restrict__ data, const cx<T>* __restrict__ tw, int64_t m_cols,
@@ -606,7 +609,18 @@ __global__ __launch_bounds__(TC * N / E) void k_strided(
     const cx<T>* lane = plane + lane_off;
 
     cx<T> a[E];
-    if constexpr (MF == 0) {
+    if constexpr (MF < 0) {
+#pragma unroll
+        for (int i = 0; i < E; ++i) {
+            const cx<T>* p = lane + uoff(i, d, H, Lo);
+            if constexpr (NT) {
+                a[i].x = __builtin_nontemporal_load(&p->x);
+                a[i].y = -__builtin_nontemporal_load(&p->y);
+            } else {
+                a[i] = conjg(*p);
+            }
+        }
+    } else if constexpr (MF == 0) {
 #pragma unroll
         for (int i = 0; i < E; ++i) {
             const cx<T>* p = lane + uoff(i, d, H, Lo);
@@ -819,7 +833,7 @@ static bool whole_lines(const void* data, int64_t m_cols, const line_map& lm, in
 template <typename T, int N, int AX, int MF>
 static hipError_t strided_ax(int sign, void* data, const void* tw, int64_t m_cols,
                              int64_t n_b, line_map lm, hipStream_t s) {
-    using SH = sshape<T, N, AX, MF != 0>;
+    using SH = sshape<T, N, AX, (MF > 0)>;
     constexpr int TC = SH::TC;
     const int64_t tiles_m = (m_cols + TC - 1) / TC;
     const int64_t blocks = tiles_m * n_b;
@@ -832,25 +846,25 @@ static hipError_t strided_ax(int sign, void* data, const void* tw, int64_t m_col
     // CU), so FP64 uses it for N = 512 and 1024 only, FP32 from N = 256.
     // Where neighbouring tiles share lines, as in the y passes, the hint
     // makes them travel twice (15-50% slower).
-    if constexpr (AX == 1 && MF == 0 && (N >= 512 || (sizeof(T) == 4 && N == 256)) &&
+    if constexpr (AX == 1 && MF <= 0 && (N >= 512 || (sizeof(T) == 4 && N == 256)) &&
                   (sizeof(T) == 4 || N <= 1024) && (TC * sizeof(cx<T>)) % 128 == 0) {
         if (whole_lines(data, m_cols, lm, 128 / int64_t(sizeof(cx<T>)))) {
-            if (sign < 0)
-                hipLaunchKernelGGL((k_strided<T, N, TC, SH::XP, -1, SH::E, 0, true>), dim3(blocks),
+            if (MF < 0 || sign < 0)
+                hipLaunchKernelGGL((k_strided<T, N, TC, SH::XP, -1, SH::E, MF, true>), dim3(blocks),
                                    threads, 0, s, static_cast<cx<T>*>(data),
                                    static_cast<const cx<T>*>(tw), m_cols, tiles_m, lm);
-            else
+            else if constexpr (MF == 0)
                 hipLaunchKernelGGL((k_strided<T, N, TC, SH::XP, +1, SH::E, 0, true>), dim3(blocks),
                                    threads, 0, s, static_cast<cx<T>*>(data),
                                    static_cast<const cx<T>*>(tw), m_cols, tiles_m, lm);
             return hipGetLastError();
         }
     }
-    if (sign < 0)
+    if (MF < 0 || sign < 0)
         hipLaunchKernelGGL((k_strided<T, N, TC, SH::XP, -1, SH::E, MF>), dim3(blocks), threads,
                            0, s, static_cast<cx<T>*>(data), static_cast<const cx<T>*>(tw),
                            m_cols, tiles_m, lm);
-    else
+    else if constexpr (MF >= 0)
         hipLaunchKernelGGL((k_strided<T, N, TC, SH::XP, +1, SH::E, MF>), dim3(blocks), threads,
                            0, s, static_cast<cx<T>*>(data), static_cast<const cx<T>*>(tw),
                            m_cols, tiles_m, lm);
@@ -860,6 +874,9 @@ static hipError_t strided_ax(int sign, void* data, const void* tw, int64_t m_col
 template <typename T, int N>
 static hipError_t strided_n(int axis, int mfma_terms, int sign, void* data, const void* tw,
                             int64_t m_cols, int64_t n_b, line_map lm, hipStream_t s) {
+    if (mfma_terms == -1)
+        return axis == 0 ? strided_ax<T, N, 0, -1>(sign, data, tw, m_cols, n_b, lm, s)
+                         : strided_ax<T, N, 1, -1>(sign, data, tw, m_cols, n_b, lm, s);
     if constexpr (sizeof(T) == 4 && N >= 32) {
         if (mfma_terms == 2)
             return axis == 0 ? strided_ax<T, N, 0, 2>(sign, data, tw, m_cols, n_b, lm, s)

@@ -216,6 +216,17 @@ class Plan(_Exec):
         self._exec(_lib.gfft_exec_x_c2c, a, int(sign))
         return pencil
 
+    def pass_copy(self, data: torch.Tensor, axis: int):
+        """Yardstick: the y (axis 0) or x (axis 1) pass's loads and stores on
+        ``data`` (its buffer for that pass), no transform: ``data`` becomes
+        its conjugate."""
+        if axis not in (0, 1):
+            raise ValueError("axis must be 0 (y pass) or 1 (x pass)")
+        n = self._ncplx() if axis == 0 else self._npencil()
+        a = self._check(data, self.cdtype, n, "data")
+        self._exec(_lib.gfft_exec_pass_copy, int(axis), a)
+        return data
+
     # ------------------------------------------------------------ in place
     def empty_inplace(self):
         """The shared buffer of an in-place plan (complex, spectrum shape)."""

@@ -7,7 +7,7 @@ import pytest
 import torch
 
 import oracle
-from helpers import host, real_input, rel_l2
+from helpers import cplx_input, host, real_input, rel_l2
 from paper_2202_12756_amd import GfftError, Plan, _lib
 
 pytestmark = pytest.mark.gpu
@@ -208,3 +208,26 @@ def test_device_copy_is_bit_exact(nbytes):
     assert torch.equal(dst[nbytes // 8:], torch.full((2,), -1, dtype=torch.int64, device="cuda"))
     with pytest.raises(ValueError):
         device_copy(dst[:3], src)
+
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32], ids=["f64", "f32"])
+@pytest.mark.parametrize("n,x", [(64, 64), (256, 256), (1024, 2)])
+def test_pass_copy_conjugates_in_place(n, x, dtype):
+    """gfft_exec_pass_copy reads and writes exactly the elements of the y
+    (axis 0) and x (axis 1) passes, storing each one's conjugate: bit-exact,
+    on full grids (the x pass's streaming kernel at N = 256 in FP32) and a
+    1024-point slab (ragged 16-column tiles)."""
+    p = Plan(n, dtype, slab_x=x) if x < n else Plan(n, dtype)
+    g, _ = cplx_input(p.spectrum_shape, 4300 + n, dtype)
+    ref = g.conj().resolve_conj()
+    p.pass_copy(g, 0)
+    torch.cuda.synchronize()
+    assert torch.equal(g, ref)
+    pen, _ = cplx_input(p.pencil_shape, 4400 + n, dtype)
+    ref = pen.conj().resolve_conj()
+    p.pass_copy(pen, 1)
+    torch.cuda.synchronize()
+    assert torch.equal(pen, ref)
+    with pytest.raises(ValueError):
+        p.pass_copy(g, 2)
+    assert _lib.gfft_exec_pass_copy(p._h, 2, g.data_ptr(), 0) == _lib.GFFT_E_INVALID_ARG

@@ -620,6 +620,8 @@ __global__ __launch_bounds__(TC * N / E) void k_strided(
                 a[i] = conjg(*p);
             }
         }
+        // all loads of the tile before any store, as in the transform
+        __syncthreads();
     } else if constexpr (MF == 0) {
 #pragma unroll
         for (int i = 0; i < E; ++i) {

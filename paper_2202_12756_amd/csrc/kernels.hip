@@ -311,11 +311,15 @@ __global__ __launch_bounds__((zshape<N / 2, EMAX, THREADS>::NT)) void k_z_c2r_pe
 // One workgroup per plane, NT = N M / 32 threads, 32 complex values per
 // thread in both phases:
 //   z phase: thread (r, t), r < N rows, t < TZ = M/32, holds z[t + TZ m] of
-//            row r (z[n] = x[2n] + i x[2n+1]); M-point FFT, real split;
+//            row r (z[n] = x[2n] + i x[2n+1]); M-point FFT;
 //   y phase: thread (s, c), c < M columns, s < TY = N/32, holds column c at
 //            rows s + TY m; N-point FFT.
 // Between the phases the plane moves through LDS, real parts then imaginary
-// parts.  The z half spectrum has M + 1 columns; kz = 0 and kz = M are real
+// parts.  The forward's real split (bin k from Z[k] and Z[M-k]) is formed
+// by the column threads as they read the transposed plane, column c taking
+// columns c and M - c from LDS; the inverse forms its pre-process the same
+// way after the transpose back, through a mirror exchange of half the rows
+// at a time.  The z half spectrum has M + 1 columns; kz = 0 and kz = M are real
 // for a real row, so they travel together as one complex column
 // P = X[.][0] + i X[.][M] (two real transforms for one complex one) and are
 // separated after the y FFT: X0 = (P + conj P(-ky)) / 2, XM = (P - conj
@@ -385,34 +389,39 @@ __global__ __launch_bounds__(plane_shape<N>::NT) void k_plane_r2c(
     for (int m = 0; m < 32; ++m) a[m] = src[t + TZ * m];
     fft_regs<float, M, 32, -1, 32>(a, t, tw, 2,
                                    xch_split<float, idx_rows<P::PS>>{lds, idx_rows<P::PS>{r * P::MP}});
-    // real split X[k] = (Z[k] + conj Z[M-k])/2 - (i/2) W_N^k (Z[k] - conj Z[M-k]),
-    // X[M] = Re Z[0] - Im Z[0]; bin multipliers applied here
-    const float x_m = (a[0].x - a[0].y) * mul_edge;  // meaningful for t == 0
-    plane_mirror<N>(lds, r, t, a, [&](int m, cx<float> zk, cx<float> zmir) {
-        const int k = t + TZ * m;
-        const cx<float> zc = conjg(zmir);
-        const cx<float> A = scal(zk + zc, 0.5f);
-        const cx<float> B = scal(zk - zc, 0.5f);
-        const cx<float> wb = cmul(tw[k], B);
-        const float f = k == 0 ? mul_edge : mul_int;
-        return cx<float>{(A.x + wb.y) * f, (A.y - wb.x) * f};
-    });
-    // kz = 0 and kz = M (both real) travel as one complex column c = 0
-    if (t == 0) a[0].y = x_m;
 
-    // rows -> columns, real then imaginary parts
+    // rows -> columns, real then imaginary parts, with the real split folded
+    // in: column thread c reads Z[y][c] and Z[y][M-c] and forms
+    //   X[c] = (Z[c] + conj Z[M-c])/2 - (i/2) W_N^c (Z[c] - conj Z[M-c])
+    // as a part from the real parts and a part from the imaginary parts
+    // (bin multipliers applied); kz = 0 and kz = M (both real, X[M] =
+    // Re Z[0] - Im Z[0]) travel as one complex column c = 0.
+    const int cm = (M - c) & (M - 1);
+    const cx<float> w = tw[c];
+    const float f = c == 0 ? mul_edge : mul_int;
     cx<float> b[32];
 #pragma unroll
     for (int m = 0; m < 32; ++m) lds[r * P::LD + t + TZ * m] = a[m].x;
     __syncthreads();
 #pragma unroll
-    for (int m = 0; m < 32; ++m) b[m].x = lds[(s + TY * m) * P::LD + c];
+    for (int m = 0; m < 32; ++m) {
+        const float zr = lds[(s + TY * m) * P::LD + c], mr = lds[(s + TY * m) * P::LD + cm];
+        const float hd = 0.5f * (zr - mr);
+        b[m] = cx<float>{0.5f * (zr + mr) + w.y * hd, -w.x * hd};
+    }
     __syncthreads();
 #pragma unroll
     for (int m = 0; m < 32; ++m) lds[r * P::LD + t + TZ * m] = a[m].y;
     __syncthreads();
 #pragma unroll
-    for (int m = 0; m < 32; ++m) b[m].y = lds[(s + TY * m) * P::LD + c];
+    for (int m = 0; m < 32; ++m) {
+        const float zi = lds[(s + TY * m) * P::LD + c], mi = lds[(s + TY * m) * P::LD + cm];
+        const float hs = 0.5f * (zi + mi);
+        const float vx = b[m].x + w.x * hs;
+        // c = 0: b[m].x holds Re Z[0], the imaginary part carries X[M]
+        const float vy = c == 0 ? b[m].x - zi : b[m].y + 0.5f * (zi - mi) + w.y * hs;
+        b[m] = cx<float>{vx * f, vy * f};
+    }
     __syncthreads();
 
     // y phase: column c, N-point FFT

@@ -127,7 +127,8 @@ def test_null_plan_and_out_pointer():
                       (_lib.gfft_exec_x_c2c, (16, -1, None)),
                       (_lib.gfft_exec_y_c2c, (16, -1, None)),
                       (_lib.gfft_exec_z_r2c, (16, 32, 1.0, 0, None)),
-                      (_lib.gfft_exec_z_c2r, (16, 32, 1.0, 0, None))):
+                      (_lib.gfft_exec_z_c2r, (16, 32, 1.0, 0, None)),
+                      (_lib.gfft_exec_pass_copy, (0, 16, None))):
         assert fn(None, *extra) == _lib.GFFT_E_INVALID_ARG
 
 

@@ -260,3 +260,19 @@ def test_pencil_x_pass_streaming_kernel(dtype):
     p.x_c2c(xp, +1)
     torch.cuda.synchronize()
     assert rel_l2(host(xp)[0], oracle.pencil_x_c2c(xpref[0], +1)) <= TOL[dtype]
+
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32], ids=["f64", "f32"])
+@pytest.mark.parametrize("grid", [(2, 4), (8, 2)])
+def test_pencil_pass_copy_conjugates(dtype, grid):
+    """gfft_exec_pass_copy on a pencil plan reads and writes exactly the
+    y-pencil (axis 0) and x-pencil (axis 1) that the y and x passes take."""
+    n, (pr, pc) = 64, grid
+    p = PencilPlan(n, dtype, grid, pc - 1)
+    stream = torch.cuda.current_stream().cuda_stream
+    for axis, shape in ((0, p.ypencil_shape), (1, p.xpencil_shape)):
+        d, _ = cplx_input(shape, 1800 + axis, dtype)
+        ref = d.conj().resolve_conj()
+        assert _lib.gfft_exec_pass_copy(p._h, axis, d.data_ptr(), stream) == _lib.GFFT_OK
+        torch.cuda.synchronize()
+        assert torch.equal(d, ref)
